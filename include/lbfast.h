@@ -1,0 +1,152 @@
+/*
+ * lbfast.h -- C ABI of the moment-represented ("lightweight") regularized
+ * lattice Boltzmann step for AMD Instinct MI355X (gfx950).
+ *
+ * Method (Lauricella et al., "LBFAST: a lightweight moment-represented
+ * lattice Boltzmann solver", arXiv 2609.09160):
+ *   - every lattice site stores only the ten second-order Hermite
+ *     coefficients a0 = p*, a1 = u (3), a2 (6, symmetric) (section 3,
+ *     "Implementation", description of the two ten-field flip/flop arrays);
+ *   - one fused step rebuilds the post-collision populations of the
+ *     neighbours from their moments (Eqs. (4a,b), (6)), pulls them (Eq. (3))
+ *     and projects them back onto the Hermite basis (Eqs. (5), (7));
+ *   - the force-consistent correction of Eq. (8) with the Guo source of
+ *     Eq. (9) closes the step.
+ *
+ * Conventions shared by every entry point
+ *   - N = nx*ny*nz sites; site index s = x + nx*(y + ny*z) (x fastest).
+ *   - A "moment array" is 10 planes of N values (structure of arrays), plane
+ *     order m = [a0, a1x, a1y, a1z, a2xx, a2yy, a2zz, a2xy, a2xz, a2yz].
+ *     a0 is the rescaled pressure p* = p/(rho cs^2), a1 the velocity and a2
+ *     the total second-order Hermite coefficient (equilibrium u u plus the
+ *     non-equilibrium part), exactly as defined under Eq. (6).  rho is the
+ *     phase density, identically 1 for one component.
+ *   - Lattice speed of sound cs^2 = 1/3, omega = 1/tau, nu = cs^2 (tau - 1/2).
+ *   - A force array is 3 planes of N values (Fx, Fy, Fz), force per unit
+ *     volume as in Eq. (9).
+ *   - Every call returns an int status (LBF_OK or a negative LBF_E_* code);
+ *     no C++ exception crosses this boundary.  On failure the call has no
+ *     effect on the handle's state, and lbfast_last_error() returns a
+ *     message for the calling thread.
+ *   - Arguments are validated on the host before any device work.
+ *   - A handle is bound to one HIP device (the current device at create) and
+ *     one HIP stream; work is enqueued asynchronously on that stream.  A
+ *     handle is not thread-safe.  Device faults surface at the next
+ *     synchronising call (get_*, reduce, sync) as LBF_E_DEVICE.
+ *   - Host arrays are copied in/out and never retained.  Device arrays passed
+ *     as "borrowed" must stay alive (and unmodified by others while a call
+ *     that reads them is in flight) until the handle is destroyed or the
+ *     array is replaced.
+ */
+#ifndef LBFAST_H_
+#define LBFAST_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBFAST_ABI_VERSION 1
+
+typedef struct lbfast_ctx* lbfast_t; /* opaque handle */
+
+/* status codes */
+enum {
+  LBF_OK = 0,
+  LBF_E_ARG = -1,         /* invalid argument (bad size, null pointer, tau<=1/2 ...) */
+  LBF_E_UNSUPPORTED = -2, /* valid request that this build does not implement */
+  LBF_E_NOMEM = -3,       /* device or host allocation failed */
+  LBF_E_DEVICE = -4,      /* HIP runtime error or kernel fault */
+  LBF_E_NONFINITE = -5,   /* a reduction found NaN/Inf in the state */
+  LBF_E_STATE = -6        /* call not valid in the handle's current state */
+};
+
+/* velocity sets, both truncated at second order (section 2, last paragraphs) */
+enum { LBF_D3Q19 = 19, LBF_D3Q27 = 27 };
+
+/* element types: storage of the moment planes, and dtype of user arrays.
+ * F16S/BF16S = 16-bit storage of v/s_m with a power-of-two scale s_m per
+ * moment plane; arithmetic is FP32 (only valid as `storage`). */
+enum { LBF_F64 = 0, LBF_F32 = 1, LBF_F16S = 2, LBF_BF16S = 3 };
+
+/* boundary per axis: periodic, or stationary halfway bounce-back walls at
+ * both ends (walls at -1/2 and n-1/2; every layer is fluid).  Walls are
+ * supported on the y axis only. */
+enum { LBF_PERIODIC = 0, LBF_WALLS = 1 };
+
+typedef struct lbfast_params {
+  uint32_t struct_size; /* = sizeof(lbfast_params) */
+  int32_t lattice;      /* LBF_D3Q19 or LBF_D3Q27 */
+  int32_t storage;      /* LBF_F64, LBF_F32, LBF_F16S, LBF_BF16S */
+  int32_t bc[3];        /* per axis x, y, z: LBF_PERIODIC or LBF_WALLS */
+  int64_t nx, ny, nz;   /* grid, each >= 1 (>= 2 on a walled axis) */
+  double tau;           /* relaxation time, > 1/2 */
+  double force[3];      /* uniform body force per unit volume (rho = 1);
+                           ignored while a force field is set */
+  float scale[10];      /* 16-bit storage only: power-of-two scale per moment
+                           plane; 0 = choose at the first set_moments as the
+                           power of two that maps 2*max|v| near 2^15 (FP16) */
+  int32_t reserved[8];  /* must be zero */
+} lbfast_params;
+
+/* ABI version of the loaded library (LBFAST_ABI_VERSION at build time). */
+int lbfast_abi_version(void);
+
+/* Bytes of one moment buffer (10 planes x N x element size), 0 on invalid
+ * params.  The memory model of section 3: M = N * n_fields * b. */
+size_t lbfast_buffer_bytes(const lbfast_params* p);
+
+/* Create a solver.  `stream` is a hipStream_t (NULL = legacy default stream).
+ * buf0/buf1: two device buffers of lbfast_buffer_bytes(p) bytes, 256-byte
+ * aligned, borrowed (caller frees after destroy); pass both NULL to have the
+ * library allocate and own them.  The state is zero (rest) after create. */
+int lbfast_create(const lbfast_params* p, void* stream, void* buf0, void* buf1,
+                  lbfast_t* out);
+int lbfast_destroy(lbfast_t h);
+
+/* Copy a moment array (10 x N, dtype LBF_F64 or LBF_F32, physical values)
+ * into / out of the current state.  on_device: 1 = device pointer, 0 = host.
+ * set converts to the storage type (round to nearest even); get converts
+ * from it.  get synchronises the stream. */
+int lbfast_set_moments(lbfast_t h, const void* m, int dtype, int on_device);
+int lbfast_get_moments(lbfast_t h, void* m, int dtype, int on_device);
+
+/* Per-site body force (3 x N device array, borrowed, static in time), the
+ * F^b term of the force split in section 2.  dtype must be the compute
+ * type: LBF_F64 for F64 storage, LBF_F32 otherwise.  NULL reverts to the
+ * uniform params.force. */
+int lbfast_set_force_field(lbfast_t h, const void* F_dev, int dtype);
+
+/* Advance n >= 0 fused steps (Eq. (7) then Eq. (8)), asynchronously. */
+int lbfast_step(lbfast_t h, int64_t n);
+
+/* Wait for the handle's stream; reports device errors. */
+int lbfast_sync(lbfast_t h);
+
+/* Deterministic FP64 sums over the current state (synchronising):
+ * out = [sum a0, sum a1x, sum a1y, sum a1z, 1/2 sum |a1|^2].
+ * Returns LBF_E_NONFINITE (out still written) if any sum is NaN/Inf. */
+int lbfast_reduce(lbfast_t h, double out[5]);
+
+/* Device pointer to the buffer holding the current state (flips every
+ * step), for zero-copy reads; valid until the next step/destroy. */
+int lbfast_state_ptr(lbfast_t h, void** dev_ptr);
+
+/* The 16-bit storage scales in use (10 floats); 1.0 for FP32/FP64. */
+int lbfast_get_scales(lbfast_t h, float out[10]);
+
+/* Launch shape: rows per tile (4, 8 or 14) and z-planes per workgroup
+ * (>= 1); 0 keeps the current value.  Results do not depend on it up to
+ * summation order within a site (they are bitwise identical: every site is
+ * computed by the same instruction sequence). */
+int lbfast_set_launch(lbfast_t h, int tile_rows, int z_chunk);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* lbfast_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBFAST_H_ */

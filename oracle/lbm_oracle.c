@@ -1,0 +1,295 @@
+/*
+ * lbm_oracle.c -- plain, slow, FP64 CPU oracle for the moment-represented
+ * regularized lattice Boltzmann step of Lauricella et al. (arXiv 2609.09160).
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or helper with the GPU library.
+ *
+ * What it computes.  The moment form of the paper (Eq. (7) followed by the
+ * correction of Eq. (8)) is, by construction, a population-based regularized
+ * LBM whose populations are never stored: Eq. (7) is Eq. (3) with the
+ * populations expanded on the second-order Hermite basis (Eqs. (4)-(6)) and
+ * projected back (Eq. (5)).  This oracle therefore stores the populations
+ * f_i explicitly (Q per site) and performs, per step:
+ *   1. moments of f (Eq. (5)), corrected as in Eq. (8):
+ *        p* = sum f,  u = sum c f + F/(2 rho),
+ *        a2 = sum H2 f + (F u + u F)/(2 rho);
+ *   2. the non-equilibrium part a2neq = a2 - u u (Eq. (6): the equilibrium
+ *      coefficients are p*, u, u u and only a2 has a non-equilibrium part);
+ *   3. the regularized post-collision population (Eq. (3) with Eq. (4)):
+ *        f_i* = feq_i + (1 - omega) fneq_i + S_i / 2,
+ *      feq_i, fneq_i from the truncated Hermite series of Eq. (4), S_i the
+ *      Guo term of Eq. (9) written as printed;
+ *   4. streaming by pull, f_i(x, t+1) = f_i*(x - c_i); on an axis with walls
+ *      a source beyond the wall is replaced by the bounce-back value
+ *      f_{-i}*(x) (stationary halfway bounce-back; the paper names no-slip
+ *      walls in section 4 but no scheme, so this is a reading).
+ * rho = 1 (one component, section 2: rho(phi) with equal phase densities).
+ *
+ * Everything is written with generic loops over directions and tensor
+ * indices so that it can be checked against the equations by eye.  The
+ * velocity sets are the textbook D3Q19 / D3Q27 (the paper defers to the
+ * textbooks for them): all c in {-1,0,1}^3 (|c|^2 <= 2 for D3Q19), weights by
+ * |c|^2.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define CS2 (1.0 / 3.0)
+
+/* Number of OpenMP threads a parallel loop of this library will use. */
+int oracle_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* Build the velocity set: enumerate {-1,0,1}^3, keep |c|^2 <= 2 for Q=19.
+ * Returns Q, or -1 for an unknown Q. */
+int oracle_lattice(int Q, int* c, double* w) {
+  double wt[4];
+  int maxc2;
+  if (Q == 19) {
+    wt[0] = 1.0 / 3.0; wt[1] = 1.0 / 18.0; wt[2] = 1.0 / 36.0; wt[3] = 0.0;
+    maxc2 = 2;
+  } else if (Q == 27) {
+    wt[0] = 8.0 / 27.0; wt[1] = 2.0 / 27.0; wt[2] = 1.0 / 54.0; wt[3] = 1.0 / 216.0;
+    maxc2 = 3;
+  } else {
+    return -1;
+  }
+  int q = 0;
+  for (int cz = -1; cz <= 1; ++cz)
+    for (int cy = -1; cy <= 1; ++cy)
+      for (int cx = -1; cx <= 1; ++cx) {
+        int c2 = cx * cx + cy * cy + cz * cz;
+        if (c2 > maxc2) continue;
+        c[3 * q + 0] = cx; c[3 * q + 1] = cy; c[3 * q + 2] = cz;
+        w[q] = wt[c2];
+        ++q;
+      }
+  return q;
+}
+
+typedef struct {
+  int Q;
+  int c[27][3];
+  double w[27];
+  int opp[27];
+} lattice_t;
+
+static int make_lattice(int Q, lattice_t* L) {
+  int cc[81];
+  if (oracle_lattice(Q, cc, L->w) != Q) return -1;
+  L->Q = Q;
+  for (int i = 0; i < Q; ++i)
+    for (int a = 0; a < 3; ++a) L->c[i][a] = cc[3 * i + a];
+  for (int i = 0; i < Q; ++i) {
+    L->opp[i] = -1;
+    for (int j = 0; j < Q; ++j)
+      if (L->c[j][0] == -L->c[i][0] && L->c[j][1] == -L->c[i][1] &&
+          L->c[j][2] == -L->c[i][2])
+        L->opp[i] = j;
+  }
+  return 0;
+}
+
+/* Hermite basis of section 2: H0 = 1, H1_a = c_a, H2_ab = c_a c_b - cs^2 d_ab */
+static double H2(const lattice_t* L, int i, int a, int b) {
+  return (double)(L->c[i][a] * L->c[i][b]) - (a == b ? CS2 : 0.0);
+}
+
+/* Step 1 and 2 at one site: corrected moments of Eq. (8) from populations.
+ * m = [p*, u(3), a2xx, a2yy, a2zz, a2xy, a2xz, a2yz]. */
+static void site_moments(const lattice_t* L, const double* fs, const double F[3],
+                         double rho, double m[10]) {
+  double p = 0.0, j[3] = {0, 0, 0}, P[3][3] = {{0}};
+  for (int i = 0; i < L->Q; ++i) {
+    p += fs[i];
+    for (int a = 0; a < 3; ++a) j[a] += L->c[i][a] * fs[i];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) P[a][b] += H2(L, i, a, b) * fs[i];
+  }
+  double u[3];
+  for (int a = 0; a < 3; ++a) u[a] = j[a] + F[a] / (2.0 * rho);
+  double a2[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      a2[a][b] = P[a][b] + (F[a] * u[b] + F[b] * u[a]) / (2.0 * rho);
+  m[0] = p;
+  m[1] = u[0]; m[2] = u[1]; m[3] = u[2];
+  m[4] = a2[0][0]; m[5] = a2[1][1]; m[6] = a2[2][2];
+  m[7] = a2[0][1]; m[8] = a2[0][2]; m[9] = a2[1][2];
+}
+
+static void unpack_a2(const double m[10], double a2[3][3]) {
+  a2[0][0] = m[4]; a2[1][1] = m[5]; a2[2][2] = m[6];
+  a2[0][1] = a2[1][0] = m[7];
+  a2[0][2] = a2[2][0] = m[8];
+  a2[1][2] = a2[2][1] = m[9];
+}
+
+/* Truncated Hermite series of Eq. (4): w_i sum_n H^(n):a^(n) / (cs^(2n) n!) */
+static double hermite_series(const lattice_t* L, int i, double a0, const double a1[3],
+                             double a2[3][3]) {
+  double s1 = 0.0, s2 = 0.0;
+  for (int a = 0; a < 3; ++a) s1 += L->c[i][a] * a1[a];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) s2 += H2(L, i, a, b) * a2[a][b];
+  return L->w[i] * (a0 + s1 / CS2 + s2 / (2.0 * CS2 * CS2));
+}
+
+/* Guo source term of Eq. (9), as printed:
+ * S_i = w_i [ (c_a - u_a)/cs^2 + (c_b u_b) c_a / cs^4 ] F_a / rho */
+static double guo_source(const lattice_t* L, int i, const double u[3], const double F[3],
+                         double rho) {
+  double cu = 0.0;
+  for (int b = 0; b < 3; ++b) cu += L->c[i][b] * u[b];
+  double s = 0.0;
+  for (int a = 0; a < 3; ++a)
+    s += ((L->c[i][a] - u[a]) / CS2 + cu * L->c[i][a] / (CS2 * CS2)) * F[a] / rho;
+  return L->w[i] * s;
+}
+
+/* Step 3 at one site: regularized post-collision populations, Eq. (3) with
+ * f^eq, f^neq from Eq. (4) and the coefficients of Eq. (6). */
+static void site_collide(const lattice_t* L, const double m[10], const double F[3],
+                         double rho, double omega, double* fpost) {
+  double u[3] = {m[1], m[2], m[3]};
+  double a2[3][3], uu[3][3], a2neq[3][3];
+  unpack_a2(m, a2);
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      uu[a][b] = u[a] * u[b];
+      a2neq[a][b] = a2[a][b] - uu[a][b];
+    }
+  const double zero3[3] = {0, 0, 0};
+  for (int i = 0; i < L->Q; ++i) {
+    double feq = hermite_series(L, i, m[0], u, uu);
+    double fneq = hermite_series(L, i, 0.0, zero3, a2neq);
+    double S = guo_source(L, i, u, F, rho);
+    fpost[i] = feq + (1.0 - omega) * fneq + 0.5 * S;
+  }
+}
+
+static void site_force(const double* F, int64_t N, int64_t s, double out[3]) {
+  if (F) {
+    out[0] = F[s]; out[1] = F[N + s]; out[2] = F[2 * N + s];
+  } else {
+    out[0] = out[1] = out[2] = 0.0;
+  }
+}
+
+/* Populations whose corrected moments (step 1) are exactly m:
+ * f_i = w_i [a0 + c.(u - F/2rho)/cs^2 + H2:(a2 - (Fu+uF)/2rho)/(2 cs^4)],
+ * i.e. Eq. (4) with the correction of Eq. (8) undone. */
+int oracle_init(int Q, int64_t nx, int64_t ny, int64_t nz, const double* m,
+                const double* F, double* f) {
+  lattice_t L;
+  if (make_lattice(Q, &L)) return -1;
+  const int64_t N = nx * ny * nz;
+  const double rho = 1.0;
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < N; ++s) {
+    double Fs[3], ms[10];
+    site_force(F, N, s, Fs);
+    for (int k = 0; k < 10; ++k) ms[k] = m[k * N + s];
+    double u[3] = {ms[1], ms[2], ms[3]};
+    double a1[3], a2[3][3];
+    unpack_a2(ms, a2);
+    for (int a = 0; a < 3; ++a) a1[a] = u[a] - Fs[a] / (2.0 * rho);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) a2[a][b] -= (Fs[a] * u[b] + Fs[b] * u[a]) / (2.0 * rho);
+    for (int i = 0; i < Q; ++i) f[i * N + s] = hermite_series(&L, i, ms[0], a1, a2);
+  }
+  return 0;
+}
+
+/* Reported (corrected) moments of a population field: step 1 at every site. */
+int oracle_moments(int Q, int64_t nx, int64_t ny, int64_t nz, const double* f,
+                   const double* F, double* m) {
+  lattice_t L;
+  if (make_lattice(Q, &L)) return -1;
+  const int64_t N = nx * ny * nz;
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < N; ++s) {
+    double fs[27], Fs[3], ms[10];
+    for (int i = 0; i < Q; ++i) fs[i] = f[i * N + s];
+    site_force(F, N, s, Fs);
+    site_moments(&L, fs, Fs, 1.0, ms);
+    for (int k = 0; k < 10; ++k) m[k * N + s] = ms[k];
+  }
+  return 0;
+}
+
+/* Steps 1-3 at every site: fpost = collide(moments(f)). */
+int oracle_collide(int Q, int64_t nx, int64_t ny, int64_t nz, double tau,
+                   const double* f, const double* F, double* fpost) {
+  lattice_t L;
+  if (make_lattice(Q, &L)) return -1;
+  const int64_t N = nx * ny * nz;
+  const double omega = 1.0 / tau;
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < N; ++s) {
+    double fs[27], Fs[3], ms[10], fp[27];
+    for (int i = 0; i < Q; ++i) fs[i] = f[i * N + s];
+    site_force(F, N, s, Fs);
+    site_moments(&L, fs, Fs, 1.0, ms);
+    site_collide(&L, ms, Fs, 1.0, omega, fp);
+    for (int i = 0; i < Q; ++i) fpost[i * N + s] = fp[i];
+  }
+  return 0;
+}
+
+/* Step 4: pull streaming with periodic wrap, or halfway bounce-back where the
+ * source lies beyond a wall (bc[a] = 1 on axis a). */
+int oracle_stream(int Q, int64_t nx, int64_t ny, int64_t nz, const int* bc,
+                  const double* fpost, double* f) {
+  lattice_t L;
+  if (make_lattice(Q, &L)) return -1;
+  const int64_t n[3] = {nx, ny, nz};
+  const int64_t N = nx * ny * nz;
+#pragma omp parallel for schedule(static)
+  for (int64_t z = 0; z < nz; ++z)
+    for (int64_t y = 0; y < ny; ++y)
+      for (int64_t x = 0; x < nx; ++x) {
+        const int64_t X[3] = {x, y, z};
+        const int64_t s = x + nx * (y + ny * z);
+        for (int i = 0; i < Q; ++i) {
+          int64_t src[3];
+          int solid = 0;
+          for (int a = 0; a < 3; ++a) {
+            src[a] = X[a] - L.c[i][a];
+            if (src[a] < 0 || src[a] >= n[a]) {
+              if (bc[a]) solid = 1;
+              src[a] = ((src[a] % n[a]) + n[a]) % n[a];
+            }
+          }
+          if (solid) {
+            f[i * N + s] = fpost[L.opp[i] * N + s];
+          } else {
+            const int64_t ss = src[0] + nx * (src[1] + ny * src[2]);
+            f[i * N + s] = fpost[i * N + ss];
+          }
+        }
+      }
+  return 0;
+}
+
+/* nsteps full steps on f (in place); scratch holds Q x N doubles. */
+int oracle_run(int Q, int64_t nx, int64_t ny, int64_t nz, const int* bc, double tau,
+               const double* F, double* f, double* scratch, int64_t nsteps) {
+  for (int64_t t = 0; t < nsteps; ++t) {
+    if (oracle_collide(Q, nx, ny, nz, tau, f, F, scratch)) return -1;
+    if (oracle_stream(Q, nx, ny, nz, bc, scratch, f)) return -1;
+  }
+  return 0;
+}
