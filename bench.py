@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Throughput of the fused moment-space LBM step on one MI355X.
+
+Default workload: D3Q19, FP32 moment storage, 512^3 periodic, tau = 0.6,
+random solenoidal initial field (|k| <= 8, rms |u| = 0.02, seed 9160).  One
+"step" is one fused stream-and-collide update of every site (one kernel
+launch).  Prints ONE JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--lattice 19|27]
+                  [--storage f32|f64|f16s|bf16s] [--n 512] [--variants]
+                  [--no-cpu-baseline] [--copy-probe]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + % HBM roofline, D3Q19 512^3 FP32 vs 16-bit moments; adjoint MLUPS"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, AMD published peak
+BYTES_PER_VALUE = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
+KERNEL_SRC = os.path.join(ROOT, "paper_2609_09160_amd", "csrc", "step_kernel.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_d3q19_f32_512.txt")
+
+
+def kernel_hash():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic(n_sites):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when absent or taken on another version of the kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        line = line.strip()
+        if line and not line.startswith("#") and "=" in line:
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_sha256_16") != kernel_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def make_input(shape, device):
+    from paper_2609_09160_amd import inputs
+    return inputs.solenoidal_field(shape, device=device)
+
+
+def time_steps(solver, steps, warmup):
+    import torch
+    solver.step(warmup)
+    solver.sync()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(solver.stream)
+    solver.step(steps)
+    end.record(solver.stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps  # ms per step (= per launch)
+
+
+def run_gpu(n, lattice, storage, steps, warmup, m0=None, launch=(0, 0)):
+    import torch
+    from paper_2609_09160_amd import Solver
+    shape = (n, n, n)
+    own = m0 is None
+    if own:
+        m0 = make_input(shape, "cuda")
+    s = Solver(shape, 0.6, lattice=lattice, storage=storage)
+    if launch != (0, 0):
+        s.set_launch(*launch)
+    s.set_moments(m0)
+    if own:
+        del m0
+    ms = time_steps(s, steps, warmup)
+    red = s.reduce()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    sites = n ** 3
+    mlups = sites / (ms * 1e-3) / 1e6
+    gbs = 20 * BYTES_PER_VALUE[storage] * sites / (ms * 1e-3) / 1e9
+    return {"mlups": mlups, "ms_per_step": ms, "algorithmic_GBs": gbs,
+            "hbm_frac": gbs / HBM_PEAK_GBS, "finite": bool(all(abs(v) < 1e300 for v in red))}
+
+
+def copy_ceiling(nbytes=4 << 30, reps=20):
+    """Device-to-device copy (torch's copy kernel) of nbytes: GB/s counting
+    read + write."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    st, en = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    st.record()
+    for _ in range(reps):
+        b.copy_(a)
+    en.record()
+    torch.cuda.synchronize()
+    ms = st.elapsed_time(en) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9, ms
+
+
+def cpu_baseline(lattice, budget_s=15.0):
+    """The FP64 CPU oracle on the host cores, bounded sample of the workload."""
+    import numpy as np
+    import oracle
+    from paper_2609_09160_amd import inputs
+    n = 128
+    shape = (n, n, n)
+    m0 = inputs.solenoidal_field(shape)
+    o = oracle.PopulationOracle(lattice, shape, 0.6)
+    o.set_moments(m0)
+    o.step(1)  # warm-up
+    t0 = time.perf_counter()
+    o.step(1)
+    one = time.perf_counter() - t0
+    k = max(1, min(40, int(budget_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    o.step(k)
+    dt = time.perf_counter() - t0
+    assert np.isfinite(o.f).all()
+    return {"value": round(n ** 3 * k / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"D3Q{lattice} FP64 population oracle, {n}^3 of the same solenoidal field, "
+                      f"tau=0.6, {k} timed steps after 2 untimed ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--lattice", type=int, default=19, choices=(19, 27))
+    ap.add_argument("--storage", default="f32", choices=tuple(BYTES_PER_VALUE))
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--variants", action="store_true",
+                    help="also time D3Q27, FP64 and 16-bit storage (short runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile-rows", type=int, default=0, help="launch override (0 = default)")
+    ap.add_argument("--z-chunk", type=int, default=0, help="launch override (0 = default)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only time a plain device copy (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the step shards by z-slabs with a one-site moment halo; not built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+
+    if args.copy_probe:
+        gbs, ms = copy_ceiling()
+        print(json.dumps({"copy_GBs": round(gbs, 1), "ms": round(ms, 4), "bytes": 4 << 30}))
+        return
+
+    from paper_2609_09160_amd import _lib
+    _lib.load()
+    n = args.n
+    sites = n ** 3
+    main_run = run_gpu(n, args.lattice, args.storage, args.steps, args.warmup,
+                       launch=(args.tile_rows, args.z_chunk))
+    ms = main_run["ms_per_step"]
+    value = main_run["mlups"]
+    bpl = 20 * BYTES_PER_VALUE[args.storage]
+    achieved = bpl * sites / (ms * 1e-3) / 1e9
+    traffic = None
+    if (n, args.lattice, args.storage) == (512, 19, "f32"):
+        traffic = read_traffic(sites)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": round(value / 2300.0, 2) if (n, args.lattice, args.storage) == (512, 19, "f32") else None,
+        "baseline_note": "paper: 2.3 GLUPS, 1x NVIDIA A100, D3Q19 FP32 512^3 (other hardware; context)",
+        "dtype": {"f64": "f64", "f32": "f32", "f16s": "f32 (fp16-scaled storage)",
+                  "bf16s": "f32 (bf16-scaled storage)"}[args.storage],
+        "data": "synthetic",
+        "config": {"workload": f"D3Q{args.lattice} {args.storage.upper()} {n}^3 periodic, tau=0.6, "
+                               "random solenoidal field |k|<=8 rms 0.02 (seed 9160)",
+                   "lattice": f"D3Q{args.lattice}", "grid": [n, n, n], "storage": args.storage},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "bytes_per_lup_algorithmic": bpl},
+    }
+    if args.variants:
+        var = {}
+        for lat, st in ((27, "f32"), (19, "f16s"), (19, "bf16s"), (27, "f16s"), (19, "f64")):
+            if (lat, st) == (args.lattice, args.storage):
+                continue
+            r = run_gpu(n, lat, st, max(20, args.steps // 4), 5)
+            var[f"d3q{lat}_{st}"] = {"mlups": round(r["mlups"], 1),
+                                     "ms_per_step": round(r["ms_per_step"], 5),
+                                     "hbm_frac": round(r["hbm_frac"], 4)}
+        gbs, _ = copy_ceiling()
+        var["device_copy_GBs"] = round(gbs, 1)
+        out["variants"] = var
+    if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
+        out["cpu_baseline"] = cpu_baseline(args.lattice)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

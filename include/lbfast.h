@@ -137,10 +137,12 @@ int lbfast_state_ptr(lbfast_t h, void** dev_ptr);
 /* The 16-bit storage scales in use (10 floats); 1.0 for FP32/FP64. */
 int lbfast_get_scales(lbfast_t h, float out[10]);
 
-/* Launch shape: rows per tile (4, 8 or 14) and z-planes per workgroup
- * (>= 1); 0 keeps the current value.  Results do not depend on it up to
- * summation order within a site (they are bitwise identical: every site is
- * computed by the same instruction sequence). */
+/* Launch shape: rows per tile (4, 6, 8 or 14; LBF_E_UNSUPPORTED if the
+ * tile's LDS would exceed 160 KiB) and z-planes per workgroup (>= 1); 0 keeps
+ * the current value.  Every shape computes the same formulas per site; the
+ * tile heights are separately compiled, so results may differ between shapes
+ * in the last bits (floating-point contraction), while one shape is bitwise
+ * reproducible from run to run. */
 int lbfast_set_launch(lbfast_t h, int tile_rows, int z_chunk);
 
 /* Message for the last failing call on this thread ("" if none). */

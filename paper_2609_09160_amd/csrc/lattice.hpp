@@ -1,0 +1,230 @@
+// lattice.hpp -- compile-time velocity sets, storage codecs and small
+// device helpers for the fused moment-space LBM step (gfx950).
+//
+// Velocity sets: D3Q19 and D3Q27, both truncated at second order (paper,
+// end of section 2).  The direction order is this library's own and is chosen
+// for the z-marching kernel: directions that move in the x-y plane
+// (c_x != 0 or c_y != 0) come first, so that their index is also their LDS
+// staging slot; the three "column" directions (0,0,0), (0,0,+1), (0,0,-1)
+// come last and never leave the thread that owns the (x, y) column.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+#include <utility>
+
+namespace lbf {
+
+// directions with c_x != 0 or c_y != 0: 16 of D3Q19, then the 8 corners of D3Q27
+constexpr int kMove[24][3] = {
+    {+1, 0, 0},  {-1, 0, 0},  {0, +1, 0},  {0, -1, 0},     // faces in x, y
+    {+1, +1, 0}, {-1, -1, 0}, {+1, -1, 0}, {-1, +1, 0},    // xy edges
+    {+1, 0, +1}, {-1, 0, -1}, {+1, 0, -1}, {-1, 0, +1},    // xz edges
+    {0, +1, +1}, {0, -1, -1}, {0, +1, -1}, {0, -1, +1},    // yz edges
+    {+1, +1, +1}, {-1, -1, -1}, {+1, +1, -1}, {-1, -1, +1},  // corners
+    {+1, -1, +1}, {-1, +1, -1}, {-1, +1, +1}, {+1, -1, -1}};
+
+template <int Q>
+struct Lat {
+  static_assert(Q == 19 || Q == 27, "D3Q19 or D3Q27");
+  static constexpr int NP = (Q == 19) ? 16 : 24;  // in-plane-moving directions
+  static constexpr int kRest = NP, kUp = NP + 1, kDown = NP + 2;
+  static constexpr int c(int i, int a) {
+    return i < NP ? kMove[i][a] : (a < 2 ? 0 : (i == kUp ? 1 : (i == kDown ? -1 : 0)));
+  }
+  static constexpr int cx(int i) { return c(i, 0); }
+  static constexpr int cy(int i) { return c(i, 1); }
+  static constexpr int cz(int i) { return c(i, 2); }
+  static constexpr int c2(int i) { return cx(i) * cx(i) + cy(i) * cy(i) + cz(i) * cz(i); }
+  // weights by |c|^2 (standard tables; cs^2 = 1/3)
+  static constexpr double w(int i) {
+    return Q == 19 ? (c2(i) == 0 ? 1.0 / 3.0 : c2(i) == 1 ? 1.0 / 18.0 : 1.0 / 36.0)
+                   : (c2(i) == 0 ? 8.0 / 27.0
+                                 : c2(i) == 1 ? 2.0 / 27.0 : c2(i) == 2 ? 1.0 / 54.0 : 1.0 / 216.0);
+  }
+  // Common denominator of the weights: w_i = k_i / D with k_i a power of two
+  // (or 3 for the D3Q19 rest weight), so that multiplying by k_i is exact or
+  // unbiased and 1/D is applied once per projected moment.  Rounded weights
+  // (e.g. fl(1/18)) would otherwise scale the projected velocity by the same
+  // (1 + eps) every step, a drift that accumulates linearly in time.
+  static constexpr int D = (Q == 19) ? 9 : 27;
+  static constexpr double k(int i) { return w(i) * D; }
+  static constexpr int opp(int i) {
+    for (int j = 0; j < Q; ++j)
+      if (cx(j) == -cx(i) && cy(j) == -cy(i) && cz(j) == -cz(i)) return j;
+    return -1;
+  }
+  // rank of direction i among the directions with c_y == s (wall bookkeeping)
+  static constexpr int rank_y(int i, int s) {
+    int r = 0;
+    for (int j = 0; j < i; ++j) r += (cy(j) == s);
+    return r;
+  }
+  static constexpr int NB = (Q == 19) ? 5 : 9;  // directions with c_y == +1 (or -1)
+};
+
+// compile-time loop: f(std::integral_constant<int, i>) for i = 0..N-1
+template <typename F, int... Is>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// x / d for a compile-time d: FP32 uses a hi + lo split of 1/d so the result
+// is the nearly correctly rounded quotient (no systematic bias); FP64 uses
+// the rounded reciprocal (bias ~1e-16 per use).
+template <int d, typename C>
+__device__ __forceinline__ C div_by(C x) {
+  if constexpr (std::is_same_v<C, float>) {
+    constexpr double r = 1.0 / d;
+    constexpr float hi = static_cast<float>(r);
+    constexpr float lo = static_cast<float>(r - static_cast<double>(hi));
+    return __builtin_fmaf(x, hi, x * lo);
+  } else {
+    return x * (1.0 / d);
+  }
+}
+
+// storage codecs: element type in HBM (T) and compute type (C)
+enum { kF64 = 0, kF32 = 1, kF16S = 2, kBF16S = 3 };
+
+// Plane accesses go through buffer resources: one scalar descriptor per
+// x-y plane (base, byte size) plus a 32-bit per-lane byte offset.  Each access
+// is a single instruction with no per-lane address arithmetic, and the
+// hardware range check against the plane size turns any out-of-range offset
+// into a zero load / dropped store instead of a fault.
+constexpr int kBufWord3 = 0x00020000;  // gfx9 family: 32-bit data format, raw access
+constexpr int kNonTemporal = 2;        // cache policy bit: nt
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), static_cast<short>(0),
+                                           static_cast<int>(bytes), kBufWord3);
+}
+
+template <typename V>
+__device__ __forceinline__ V buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (sizeof(V) == 2) {
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+  } else if constexpr (sizeof(V) == 4) {
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  } else {
+    static_assert(sizeof(V) == 8, "2, 4 or 8 bytes");
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  }
+}
+
+template <typename V>
+__device__ __forceinline__ void buf_store_nt(V v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (sizeof(V) == 2) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, off, 0,
+                                          kNonTemporal);
+  } else if constexpr (sizeof(V) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0,
+                                          kNonTemporal);
+  } else {
+    static_assert(sizeof(V) == 8, "2, 4 or 8 bytes");
+    using U2 = unsigned int __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, off, 0, kNonTemporal);
+  }
+}
+
+template <int ST>
+struct Storage;
+template <>
+struct Storage<kF64> {
+  using T = double;
+  using C = double;
+  static __device__ __forceinline__ C load(const T* p, int64_t i, float) { return p[i]; }
+  static __device__ __forceinline__ C decode(T q, float) { return q; }
+  static __device__ __forceinline__ void store(T* p, int64_t i, C v, float) {
+    __builtin_nontemporal_store(v, p + i);
+  }
+  static __device__ __forceinline__ void store_at(__amdgpu_buffer_rsrc_t r, uint32_t off, C v,
+                                                 float) {
+    buf_store_nt<T>(v, r, off);
+  }
+};
+template <>
+struct Storage<kF32> {
+  using T = float;
+  using C = float;
+  static __device__ __forceinline__ C load(const T* p, int64_t i, float) { return p[i]; }
+  static __device__ __forceinline__ C decode(T q, float) { return q; }
+  static __device__ __forceinline__ void store(T* p, int64_t i, C v, float) {
+    __builtin_nontemporal_store(v, p + i);
+  }
+  static __device__ __forceinline__ void store_at(__amdgpu_buffer_rsrc_t r, uint32_t off, C v,
+                                                 float) {
+    buf_store_nt<T>(v, r, off);
+  }
+};
+
+// IEEE binary16, value = s * q; conversion rounds to nearest even
+__device__ __forceinline__ uint16_t f32_to_f16_bits(float v) {
+  return __builtin_bit_cast(uint16_t, static_cast<_Float16>(v));
+}
+__device__ __forceinline__ float f16_bits_to_f32(uint16_t q) {
+  return static_cast<float>(__builtin_bit_cast(_Float16, q));
+}
+// bfloat16 (upper half of binary32), round to nearest even; NaN stays NaN
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float v) {
+  uint32_t u = __float_as_uint(v);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t q) {
+  return __uint_as_float(static_cast<uint32_t>(q) << 16);
+}
+
+template <>
+struct Storage<kF16S> {
+  using T = uint16_t;
+  using C = float;
+  static __device__ __forceinline__ C load(const T* p, int64_t i, float s) {
+    return f16_bits_to_f32(p[i]) * s;
+  }
+  static __device__ __forceinline__ C decode(T q, float s) { return f16_bits_to_f32(q) * s; }
+  static __device__ __forceinline__ void store(T* p, int64_t i, C v, float inv_s) {
+    __builtin_nontemporal_store(f32_to_f16_bits(v * inv_s), p + i);
+  }
+  static __device__ __forceinline__ void store_at(__amdgpu_buffer_rsrc_t r, uint32_t off, C v,
+                                                 float inv_s) {
+    buf_store_nt<T>(f32_to_f16_bits(v * inv_s), r, off);
+  }
+};
+template <>
+struct Storage<kBF16S> {
+  using T = uint16_t;
+  using C = float;
+  static __device__ __forceinline__ C load(const T* p, int64_t i, float s) {
+    return bf16_bits_to_f32(p[i]) * s;
+  }
+  static __device__ __forceinline__ C decode(T q, float s) { return bf16_bits_to_f32(q) * s; }
+  static __device__ __forceinline__ void store(T* p, int64_t i, C v, float inv_s) {
+    __builtin_nontemporal_store(f32_to_bf16_bits(v * inv_s), p + i);
+  }
+  static __device__ __forceinline__ void store_at(__amdgpu_buffer_rsrc_t r, uint32_t off, C v,
+                                                 float inv_s) {
+    buf_store_nt<T>(f32_to_bf16_bits(v * inv_s), r, off);
+  }
+};
+
+// periodic index for v in [-n, 2n)
+__device__ __forceinline__ int wrap(int v, int n) {
+  v = v < 0 ? v + n : v;
+  return v >= n ? v - n : v;
+}
+// periodic index for any v
+__device__ __forceinline__ int pmod(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+}  // namespace lbf

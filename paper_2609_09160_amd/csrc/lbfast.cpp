@@ -1,0 +1,491 @@
+// lbfast.cpp -- host runtime behind the C ABI of include/lbfast.h: argument
+// validation, buffer ownership, flip/flop bookkeeping (the paper's two
+// ten-field arrays, section 3), launch shape, conversions and reductions.
+#include "lbfast.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(LBF_E_DEVICE, "%s: %s (%d)", what, hipGetErrorString(e), static_cast<int>(e));
+}
+
+size_t elem_bytes(int storage) {
+  switch (storage) {
+    case LBF_F64: return 8;
+    case LBF_F32: return 4;
+    case LBF_F16S:
+    case LBF_BF16S: return 2;
+    default: return 0;
+  }
+}
+
+bool is_pow2_float(float s) {
+  if (!(s > 0.0f) || !std::isfinite(s)) return false;
+  int e;
+  return std::frexp(s, &e) == 0.5f;
+}
+
+int validate(const lbfast_params* p) {
+  if (!p) return fail(LBF_E_ARG, "params is NULL");
+  if (p->struct_size != sizeof(lbfast_params))
+    return fail(LBF_E_ARG, "params.struct_size = %u, expected %zu", p->struct_size,
+                sizeof(lbfast_params));
+  if (p->lattice != LBF_D3Q19 && p->lattice != LBF_D3Q27)
+    return fail(LBF_E_ARG, "lattice must be 19 or 27 (got %d)", p->lattice);
+  if (elem_bytes(p->storage) == 0) return fail(LBF_E_ARG, "unknown storage %d", p->storage);
+  const int64_t n[3] = {p->nx, p->ny, p->nz};
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] < 1) return fail(LBF_E_ARG, "grid extent %d is %lld (must be >= 1)", a,
+                              static_cast<long long>(n[a]));
+    if (n[a] > (1 << 30)) return fail(LBF_E_ARG, "grid extent %d too large", a);
+    if (p->bc[a] != LBF_PERIODIC && p->bc[a] != LBF_WALLS)
+      return fail(LBF_E_ARG, "bc[%d] = %d is not LBF_PERIODIC/LBF_WALLS", a, p->bc[a]);
+  }
+  if (p->bc[0] == LBF_WALLS || p->bc[2] == LBF_WALLS)
+    return fail(LBF_E_UNSUPPORTED, "walls are supported on the y axis only");
+  if (p->bc[1] == LBF_WALLS && p->ny < 2)
+    return fail(LBF_E_ARG, "a walled axis needs at least 2 sites (ny = %lld)",
+                static_cast<long long>(p->ny));
+  const double N = static_cast<double>(p->nx) * static_cast<double>(p->ny) * static_cast<double>(p->nz);
+  if (N > 4.0e9) return fail(LBF_E_ARG, "grid has %.3g sites (limit 4e9)", N);
+  // in-plane byte offsets are 32-bit in the kernels (8-byte elements worst case)
+  if (static_cast<double>(p->nx) * static_cast<double>(p->ny) * 8.0 >= 4294967296.0)
+    return fail(LBF_E_ARG, "nx*ny too large (an x-y plane of 8-byte values must fit in 4 GiB)");
+  if (!(p->tau > 0.5) || !std::isfinite(p->tau))
+    return fail(LBF_E_ARG, "tau must be a finite value > 1/2 (got %g)", p->tau);
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(p->force[a])) return fail(LBF_E_ARG, "force[%d] is not finite", a);
+  const bool s16 = p->storage == LBF_F16S || p->storage == LBF_BF16S;
+  for (int k = 0; k < 10; ++k) {
+    if (p->scale[k] == 0.0f) continue;
+    if (!s16) return fail(LBF_E_ARG, "scale[] is only meaningful for 16-bit storage");
+    if (!is_pow2_float(p->scale[k]))
+      return fail(LBF_E_ARG, "scale[%d] = %g is not a positive power of two", k, p->scale[k]);
+  }
+  for (int k = 0; k < 8; ++k)
+    if (p->reserved[k] != 0) return fail(LBF_E_ARG, "reserved[%d] must be zero", k);
+  return LBF_OK;
+}
+
+}  // namespace
+
+struct lbfast_ctx {
+  lbfast_params p;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void* buf[2] = {nullptr, nullptr};
+  bool owned = false;
+  int cur = 0;
+  const void* Ffield = nullptr;
+  float scale[10];
+  float inv_scale[10];
+  bool scales_fixed = false;
+  int tile_rows = 8;
+  int z_chunk = 0;
+  double* d_partials = nullptr;  // kReduceBlocks*5 + 5 doubles
+  unsigned* d_maxbits = nullptr; // 10
+  int64_t N = 0;
+};
+
+namespace {
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// LDS of one step workgroup: staged populations x (rows + 2) x 66 columns
+size_t lds_bytes(int Q, int storage, int tile_rows) {
+  const size_t np = (Q == LBF_D3Q19) ? 16 : 24;
+  const size_t c = (storage == LBF_F64) ? 8 : 4;
+  return c * np * static_cast<size_t>(tile_rows + 2) * 66;
+}
+
+// default launch shape (measured on MI355X at 512^3): 8-row tiles for 32- and
+// 16-bit storage, 6-row tiles for FP64; z-chunks only when the column tiles
+// alone give fewer than ~512 workgroups (two per CU)
+void default_launch(lbfast_ctx* h) {
+  h->tile_rows = (h->p.storage == LBF_F64) ? 6 : 8;
+  h->z_chunk = 0;
+}
+
+int resolve_zchunk(const lbfast_ctx* h, int* tiles_x, int* tiles_y, int* zchunks, int* zchunk) {
+  *tiles_x = static_cast<int>(ceil_div(h->p.nx, 64));
+  *tiles_y = static_cast<int>(ceil_div(h->p.ny, h->tile_rows));
+  const int64_t cols = static_cast<int64_t>(*tiles_x) * *tiles_y;
+  int64_t zc = h->z_chunk;
+  if (zc <= 0) {
+    const int64_t want = ceil_div(512, cols);                  // chunks for ~512 blocks
+    const int64_t maxc = h->p.nz >= 8 ? h->p.nz / 8 : 1;      // chunks of >= 8 planes
+    const int64_t nchunks = want < 1 ? 1 : (want > maxc ? maxc : want);
+    zc = ceil_div(h->p.nz, nchunks);
+  }
+  if (zc > h->p.nz) zc = h->p.nz;
+  *zchunk = static_cast<int>(zc);
+  *zchunks = static_cast<int>(ceil_div(h->p.nz, zc));
+  if (static_cast<int64_t>(*zchunks) * cols > 0x7fffffff) return fail(LBF_E_ARG, "grid too large");
+  return LBF_OK;
+}
+
+int check_handle(lbfast_t h) {
+  if (!h) return fail(LBF_E_ARG, "handle is NULL");
+  return LBF_OK;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int now;
+    if (prev >= 0 && hipGetDevice(&now) == hipSuccess && now != prev) (void)hipSetDevice(prev);
+  }
+};
+
+bool is_device_ptr(const void* p) {
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbfast_abi_version(void) { return LBFAST_ABI_VERSION; }
+
+size_t lbfast_buffer_bytes(const lbfast_params* p) {
+  if (validate(p) != LBF_OK) return 0;
+  return static_cast<size_t>(p->nx) * static_cast<size_t>(p->ny) * static_cast<size_t>(p->nz) *
+         10u * elem_bytes(p->storage);
+}
+
+const char* lbfast_last_error(void) { return g_err.c_str(); }
+
+int lbfast_create(const lbfast_params* p, void* stream, void* buf0, void* buf1, lbfast_t* out) {
+  g_err.clear();
+  if (!out) return fail(LBF_E_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = validate(p);
+  if (rc != LBF_OK) return rc;
+  if ((buf0 == nullptr) != (buf1 == nullptr))
+    return fail(LBF_E_ARG, "pass both buffers or neither");
+  if (buf0 && buf0 == buf1) return fail(LBF_E_ARG, "buf0 and buf1 must differ");
+  if ((buf0 && (reinterpret_cast<uintptr_t>(buf0) & 255)) ||
+      (buf1 && (reinterpret_cast<uintptr_t>(buf1) & 255)))
+    return fail(LBF_E_ARG, "buffers must be 256-byte aligned");
+
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+
+  lbfast_ctx* h = new (std::nothrow) lbfast_ctx();
+  if (!h) return fail(LBF_E_NOMEM, "host allocation failed");
+  h->p = *p;
+  h->device = dev;
+  h->stream = static_cast<hipStream_t>(stream);
+  h->N = p->nx * p->ny * p->nz;
+  const size_t bytes = lbfast_buffer_bytes(p);
+  for (int k = 0; k < 10; ++k) {
+    h->scale[k] = (p->scale[k] != 0.0f) ? p->scale[k] : 1.0f;
+    h->inv_scale[k] = 1.0f / h->scale[k];
+  }
+  const bool s16 = p->storage == LBF_F16S || p->storage == LBF_BF16S;
+  h->scales_fixed = !s16;
+  if (s16) {
+    bool all = true;
+    for (int k = 0; k < 10; ++k) all = all && p->scale[k] != 0.0f;
+    h->scales_fixed = all;
+  }
+  default_launch(h);
+
+  if (buf0) {
+    h->buf[0] = buf0;
+    h->buf[1] = buf1;
+    h->owned = false;
+  } else {
+    h->owned = true;
+    for (int i = 0; i < 2; ++i) {
+      e = hipMalloc(&h->buf[i], bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (h->buf[0]) (void)hipFree(h->buf[0]);
+        delete h;
+        return fail(LBF_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
+      }
+    }
+  }
+  e = hipMalloc(reinterpret_cast<void**>(&h->d_partials),
+                (lbf::kReduceBlocks * 5 + 5) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&h->d_maxbits), 16 * sizeof(unsigned));
+  if (e == hipSuccess) e = hipMemsetAsync(h->buf[0], 0, bytes, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->buf[1], 0, bytes, h->stream);
+  if (e != hipSuccess) {
+    int r = hip_fail(e, "create");
+    lbfast_destroy(h);
+    return r;
+  }
+  *out = h;
+  return LBF_OK;
+}
+
+int lbfast_destroy(lbfast_t h) {
+  if (!h) return LBF_OK;
+  DeviceGuard g(h->device);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  else (void)hipDeviceSynchronize();
+  if (h->owned) {
+    if (h->buf[0]) (void)hipFree(h->buf[0]);
+    if (h->buf[1]) (void)hipFree(h->buf[1]);
+  }
+  if (h->d_partials) (void)hipFree(h->d_partials);
+  if (h->d_maxbits) (void)hipFree(h->d_maxbits);
+  delete h;
+  return LBF_OK;
+}
+
+int lbfast_set_moments(lbfast_t h, const void* m, int dtype, int on_device) {
+  g_err.clear();
+  if (int rc = check_handle(h)) return rc;
+  if (!m) return fail(LBF_E_ARG, "moment array is NULL");
+  if (dtype != LBF_F64 && dtype != LBF_F32) return fail(LBF_E_ARG, "dtype must be F64 or F32");
+  if (on_device != 0 && on_device != 1) return fail(LBF_E_ARG, "on_device must be 0 or 1");
+  DeviceGuard g(h->device);
+  const size_t ub = (dtype == LBF_F64) ? 8 : 4;
+  const int64_t N = h->N;
+  hipError_t e = hipSuccess;
+  void* staging = nullptr;
+  if (!on_device) {
+    e = hipMalloc(&staging, static_cast<size_t>(N) * ub);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(LBF_E_NOMEM, "staging allocation failed");
+    }
+  }
+  auto plane_src = [&](int k) -> const void* {
+    return static_cast<const char*>(m) + static_cast<size_t>(k) * N * ub;
+  };
+  // automatic 16-bit scales: power of two placing 2*max|v| just below 2^15
+  if (!h->scales_fixed) {
+    e = hipMemsetAsync(h->d_maxbits, 0, 16 * sizeof(unsigned), h->stream);
+    for (int k = 0; k < 10 && e == hipSuccess; ++k) {
+      const void* src = plane_src(k);
+      if (!on_device) {
+        e = hipMemcpyAsync(staging, src, N * ub, hipMemcpyHostToDevice, h->stream);
+        src = staging;
+      }
+      if (e == hipSuccess) e = lbf::launch_maxabs(dtype, src, N, k, 1, h->d_maxbits, h->stream);
+    }
+    unsigned bits[16];
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(bits, h->d_maxbits, sizeof bits, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) {
+      for (int k = 0; k < 10; ++k) {
+        if (h->p.scale[k] != 0.0f) continue;
+        float mx;
+        std::memcpy(&mx, &bits[k], sizeof mx);
+        float s = 1.0f;
+        if (mx > 0.0f && std::isfinite(mx)) {
+          int ex;
+          std::frexp(2.0f * mx, &ex);        // 2*mx in [2^(ex-1), 2^ex)
+          s = std::ldexp(1.0f, ex - 15);     // 2*mx / s < 2^15
+        }
+        h->scale[k] = s;
+        h->inv_scale[k] = 1.0f / s;
+      }
+      h->scales_fixed = true;
+    }
+  }
+  void* dst = h->buf[h->cur];
+  if (e == hipSuccess) {
+    if (on_device) {
+      e = lbf::launch_encode(h->p.storage, dtype, m, dst, N, 0, 10, h->inv_scale, h->stream);
+    } else {
+      for (int k = 0; k < 10 && e == hipSuccess; ++k) {
+        e = hipMemcpyAsync(staging, plane_src(k), N * ub, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess)
+          e = lbf::launch_encode(h->p.storage, dtype, staging, dst, N, k, 1, h->inv_scale,
+                                 h->stream);
+      }
+    }
+  }
+  if (staging) {
+    hipError_t e2 = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = e2;
+    (void)hipFree(staging);
+  }
+  if (e != hipSuccess) return hip_fail(e, "set_moments");
+  return LBF_OK;
+}
+
+int lbfast_get_moments(lbfast_t h, void* m, int dtype, int on_device) {
+  g_err.clear();
+  if (int rc = check_handle(h)) return rc;
+  if (!m) return fail(LBF_E_ARG, "moment array is NULL");
+  if (dtype != LBF_F64 && dtype != LBF_F32) return fail(LBF_E_ARG, "dtype must be F64 or F32");
+  if (on_device != 0 && on_device != 1) return fail(LBF_E_ARG, "on_device must be 0 or 1");
+  DeviceGuard g(h->device);
+  const size_t ub = (dtype == LBF_F64) ? 8 : 4;
+  const int64_t N = h->N;
+  const void* src = h->buf[h->cur];
+  hipError_t e = hipSuccess;
+  if (on_device) {
+    e = lbf::launch_decode(h->p.storage, dtype, src, m, N, 0, 10, h->scale, h->stream);
+  } else {
+    void* staging = nullptr;
+    e = hipMalloc(&staging, static_cast<size_t>(N) * ub);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(LBF_E_NOMEM, "staging allocation failed");
+    }
+    for (int k = 0; k < 10 && e == hipSuccess; ++k) {
+      e = lbf::launch_decode(h->p.storage, dtype, src, staging, N, k, 1, h->scale, h->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(static_cast<char*>(m) + static_cast<size_t>(k) * N * ub, staging,
+                           N * ub, hipMemcpyDeviceToHost, h->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    }
+    hipError_t e2 = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = e2;
+    (void)hipFree(staging);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "get_moments");
+  return LBF_OK;
+}
+
+int lbfast_set_force_field(lbfast_t h, const void* F_dev, int dtype) {
+  g_err.clear();
+  if (int rc = check_handle(h)) return rc;
+  if (!F_dev) {
+    h->Ffield = nullptr;
+    return LBF_OK;
+  }
+  const int want = (h->p.storage == LBF_F64) ? LBF_F64 : LBF_F32;
+  if (dtype != want)
+    return fail(LBF_E_ARG, "force field dtype must be the compute type (%s)",
+                want == LBF_F64 ? "F64" : "F32");
+  if (reinterpret_cast<uintptr_t>(F_dev) & (dtype == LBF_F64 ? 7 : 3))
+    return fail(LBF_E_ARG, "force field is misaligned");
+  if (!is_device_ptr(F_dev)) return fail(LBF_E_ARG, "force field must be device memory");
+  h->Ffield = F_dev;
+  return LBF_OK;
+}
+
+int lbfast_set_launch(lbfast_t h, int tile_rows, int z_chunk) {
+  g_err.clear();
+  if (int rc = check_handle(h)) return rc;
+  if (tile_rows != 0) {
+    bool ok = false;
+    for (int t : lbf::kTileRowsSupported) ok = ok || t == tile_rows;
+    if (!ok) return fail(LBF_E_ARG, "tile_rows %d not supported (4, 6, 8 or 14)", tile_rows);
+    if (lds_bytes(h->p.lattice, h->p.storage, tile_rows) > 160 * 1024)
+      return fail(LBF_E_UNSUPPORTED, "tile_rows %d needs %zu bytes of LDS (limit 160 KiB)",
+                  tile_rows, lds_bytes(h->p.lattice, h->p.storage, tile_rows));
+  }
+  if (z_chunk < 0) return fail(LBF_E_ARG, "z_chunk must be >= 0");
+  if (tile_rows) h->tile_rows = tile_rows;
+  if (z_chunk) h->z_chunk = z_chunk;
+  return LBF_OK;
+}
+
+int lbfast_step(lbfast_t h, int64_t n) {
+  g_err.clear();
+  if (int rc = check_handle(h)) return rc;
+  if (n < 0) return fail(LBF_E_ARG, "n must be >= 0");
+  if (n == 0) return LBF_OK;
+  if (!h->scales_fixed) return fail(LBF_E_STATE, "16-bit scales not set: call set_moments first");
+  DeviceGuard g(h->device);
+  lbf::StepArgs a;
+  a.nx = static_cast<int>(h->p.nx);
+  a.ny = static_cast<int>(h->p.ny);
+  a.nz = static_cast<int>(h->p.nz);
+  a.N = h->N;
+  if (int rc = resolve_zchunk(h, &a.tiles_x, &a.tiles_y, &a.zchunks, &a.zchunk)) return rc;
+  a.omega = 1.0 / h->p.tau;
+  for (int k = 0; k < 3; ++k) a.F[k] = h->Ffield ? 0.0 : h->p.force[k];
+  for (int k = 0; k < 10; ++k) {
+    a.scale[k] = h->scale[k];
+    a.inv_scale[k] = h->inv_scale[k];
+  }
+  a.Ffield = h->Ffield;
+  const bool walls_y = h->p.bc[1] == LBF_WALLS;
+  for (int64_t s = 0; s < n; ++s) {
+    a.src = h->buf[h->cur];
+    a.dst = h->buf[h->cur ^ 1];
+    hipError_t e = lbf::launch_step(h->p.lattice, h->p.storage, h->tile_rows, walls_y, a, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "step launch");
+    h->cur ^= 1;
+  }
+  return LBF_OK;
+}
+
+int lbfast_sync(lbfast_t h) {
+  g_err.clear();
+  if (int rc = check_handle(h)) return rc;
+  DeviceGuard g(h->device);
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "sync");
+  return LBF_OK;
+}
+
+int lbfast_reduce(lbfast_t h, double out[5]) {
+  g_err.clear();
+  if (int rc = check_handle(h)) return rc;
+  if (!out) return fail(LBF_E_ARG, "out is NULL");
+  DeviceGuard g(h->device);
+  double* d_out = h->d_partials + lbf::kReduceBlocks * 5;
+  hipError_t e = lbf::launch_reduce(h->p.storage, h->buf[h->cur], h->N, h->scale, h->d_partials,
+                                    d_out, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, d_out, 5 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "reduce");
+  for (int k = 0; k < 5; ++k)
+    if (!std::isfinite(out[k])) return fail(LBF_E_NONFINITE, "non-finite sum %d in the state", k);
+  return LBF_OK;
+}
+
+int lbfast_state_ptr(lbfast_t h, void** dev_ptr) {
+  g_err.clear();
+  if (int rc = check_handle(h)) return rc;
+  if (!dev_ptr) return fail(LBF_E_ARG, "dev_ptr is NULL");
+  *dev_ptr = h->buf[h->cur];
+  return LBF_OK;
+}
+
+int lbfast_get_scales(lbfast_t h, float out[10]) {
+  g_err.clear();
+  if (int rc = check_handle(h)) return rc;
+  if (!out) return fail(LBF_E_ARG, "out is NULL");
+  for (int k = 0; k < 10; ++k) out[k] = h->scale[k];
+  return LBF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,10 @@
+// step_bf16s.hip -- instantiation unit of the fused step for one storage type
+// (split so the variants compile in parallel).
+#include "step_kernel.hpp"
+
+namespace lbf {
+hipError_t launch_step_bf16s(int Q, int tile_rows, bool walls_y, bool ffield, const StepArgs& a,
+                          hipStream_t s) {
+  return launch_step_storage<kBF16S>(Q, tile_rows, walls_y, ffield, a, s);
+}
+}  // namespace lbf

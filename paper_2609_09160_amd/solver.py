@@ -1,0 +1,137 @@
+"""Python front end of the C ABI: device memory and streams come from torch,
+every step of the method runs in liblbfast.so."""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import check
+
+N_MOMENTS = 10
+MOMENT_NAMES = ("p*", "ux", "uy", "uz", "a2xx", "a2yy", "a2zz", "a2xy", "a2xz", "a2yz")
+
+
+class Solver:
+    """One moment-represented LBM lattice on one GPU.
+
+    shape = (nx, ny, nz); storage in {"f64", "f32", "f16s", "bf16s"};
+    bc = per-axis 0 (periodic) / 1 (walls, y only); force = uniform body force.
+    The two flip/flop moment buffers are torch allocations on `device`, the
+    launches go to torch's current stream of that device.
+    """
+
+    def __init__(self, shape, tau, lattice=19, storage="f32", bc=(0, 0, 0),
+                 force=(0.0, 0.0, 0.0), scale=None, device=None):
+        import torch
+        self._torch = torch
+        self.lib = _lib.load()
+        self.shape = tuple(int(v) for v in shape)
+        self.N = self.shape[0] * self.shape[1] * self.shape[2]
+        self.storage = storage
+        self.compute_dtype = torch.float64 if storage == "f64" else torch.float32
+        self.device = torch.device(device if device is not None else "cuda")
+        self.params = _lib.make_params(self.shape, tau, lattice, storage, bc, force, scale)
+        nbytes = self.lib.lbfast_buffer_bytes(ctypes.byref(self.params))
+        if nbytes == 0:
+            check(_lib.LBF_E_ARG)
+        self._bufs = [torch.empty(nbytes, dtype=torch.uint8, device=self.device) for _ in range(2)]
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        check(self.lib.lbfast_create(ctypes.byref(self.params),
+                                     ctypes.c_void_p(self.stream.cuda_stream),
+                                     ctypes.c_void_p(self._bufs[0].data_ptr()),
+                                     ctypes.c_void_p(self._bufs[1].data_ptr()), ctypes.byref(h)))
+        self.h = h
+        self._force_field = None
+
+    # -- state -----------------------------------------------------------------
+    def _as_moments(self, m):
+        torch = self._torch
+        if isinstance(m, np.ndarray):
+            m = torch.from_numpy(np.ascontiguousarray(m))
+        if m.dtype not in (torch.float64, torch.float32):
+            raise TypeError("moments must be float64 or float32")
+        if m.numel() != N_MOMENTS * self.N:
+            raise ValueError(f"expected 10 x {self.N} values, got {tuple(m.shape)}")
+        return m.contiguous()
+
+    def set_moments(self, m):
+        """m: [10, nz, ny, nx] (or [10, N]) float64/float32, host or device."""
+        torch = self._torch
+        m = self._as_moments(m)
+        dt = _lib.LBF_F64 if m.dtype == torch.float64 else _lib.LBF_F32
+        on_dev = 1 if m.is_cuda else 0
+        check(self.lib.lbfast_set_moments(self.h, ctypes.c_void_p(m.data_ptr()), dt, on_dev))
+        if on_dev:
+            self.sync()
+
+    def moments(self, dtype=None, out=None):
+        """Current state as a device tensor [10, nz, ny, nx] (float64 default)."""
+        torch = self._torch
+        dtype = dtype or torch.float64
+        nx, ny, nz = self.shape
+        if out is None:
+            out = torch.empty((N_MOMENTS, nz, ny, nx), dtype=dtype, device=self.device)
+        dt = _lib.LBF_F64 if out.dtype == torch.float64 else _lib.LBF_F32
+        check(self.lib.lbfast_get_moments(self.h, ctypes.c_void_p(out.data_ptr()), dt, 1))
+        return out
+
+    def moments_host(self, dtype=np.float64):
+        nx, ny, nz = self.shape
+        out = np.empty((N_MOMENTS, nz, ny, nx), dtype=dtype)
+        dt = _lib.LBF_F64 if dtype == np.float64 else _lib.LBF_F32
+        check(self.lib.lbfast_get_moments(self.h, out.ctypes.data_as(ctypes.c_void_p), dt, 0))
+        return out
+
+    def set_force_field(self, F):
+        """Per-site force [3, nz, ny, nx] device tensor of the compute dtype (kept
+        alive by this object), or None for the uniform force."""
+        torch = self._torch
+        if F is None:
+            check(self.lib.lbfast_set_force_field(self.h, None, 0))
+            self._force_field = None
+            return
+        F = F.to(device=self.device, dtype=self.compute_dtype).contiguous()
+        if F.numel() != 3 * self.N:
+            raise ValueError("force field must have 3 x N values")
+        dt = _lib.LBF_F64 if F.dtype == torch.float64 else _lib.LBF_F32
+        check(self.lib.lbfast_set_force_field(self.h, ctypes.c_void_p(F.data_ptr()), dt))
+        self._force_field = F
+
+    def set_launch(self, tile_rows=0, z_chunk=0):
+        check(self.lib.lbfast_set_launch(self.h, int(tile_rows), int(z_chunk)))
+
+    def scales(self):
+        out = (ctypes.c_float * 10)()
+        check(self.lib.lbfast_get_scales(self.h, out))
+        return np.array(out[:], dtype=np.float32)
+
+    # -- time stepping -----------------------------------------------------------
+    def step(self, n=1):
+        check(self.lib.lbfast_step(self.h, int(n)))
+
+    def sync(self):
+        check(self.lib.lbfast_sync(self.h))
+
+    def reduce(self):
+        """FP64 [sum p*, sum ux, sum uy, sum uz, 1/2 sum |u|^2]."""
+        out = (ctypes.c_double * 5)()
+        rc = self.lib.lbfast_reduce(self.h, out)
+        check(rc)
+        return np.array(out[:])
+
+    def state_ptr(self):
+        p = ctypes.c_void_p()
+        check(self.lib.lbfast_state_ptr(self.h, ctypes.byref(p)))
+        return p.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lbfast_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

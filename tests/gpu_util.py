@@ -1,0 +1,62 @@
+"""Shared helpers of the GPU tests: run the HIP path and the CPU oracle on the
+same seeded inputs and measure their difference."""
+import sys
+
+import numpy as np
+
+GROUPS = ((0, 1), (1, 4), (4, 10))  # p*, u, a2
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_run(shape, tau, m0, steps, lattice=19, storage="f64", bc=(0, 0, 0), force=(0, 0, 0),
+            Ffield=None, launch=None, scale=None):
+    """Run the HIP path; returns host float64 moments [10, nz, ny, nx]."""
+    import torch
+    from paper_2609_09160_amd import Solver
+    s = Solver(shape, tau, lattice=lattice, storage=storage, bc=bc, force=force, scale=scale)
+    if launch:
+        s.set_launch(*launch)
+    s.set_moments(np.ascontiguousarray(m0))
+    if Ffield is not None:
+        s.set_force_field(torch.as_tensor(Ffield, device="cuda"))
+    s.step(steps)
+    out = s.moments().cpu().numpy()
+    s.close()
+    return out
+
+
+def oracle_run(shape, tau, m0, steps, lattice=19, bc=(0, 0, 0), force=None):
+    import oracle
+    o = oracle.PopulationOracle(lattice, shape, tau, bc=bc, force=force)
+    o.set_moments(m0)
+    o.step(steps)
+    return o.moments()
+
+
+def state_rel_err(got, want):
+    """max|got - want| over all moments / max|want| over all moments, and the
+    same for the velocity group alone; rounding scales with the state's
+    magnitude, so a moment that has decayed far below the others is judged
+    against the state, not against itself."""
+    st = float(np.abs(got - want).max() / np.abs(want).max())
+    vel = float(np.abs(got[1:4] - want[1:4]).max() / np.abs(want[1:4]).max())
+    return max(st, vel)
+
+
+def group_rel_err(got, want):
+    """Max over the groups (p*, u, a2) of max|got - want| / max|want in group|
+    (a sub-array of fewer than 10 moments is one group)."""
+    err = 0.0
+    for lo, hi in (GROUPS if len(want) == 10 else ((0, len(want)),)):
+        ref = np.abs(want[lo:hi]).max()
+        d = np.abs(got[lo:hi] - want[lo:hi]).max()
+        err = max(err, d / ref if ref > 0 else d)
+    return err
+
+
+def u_rel_l2(got, want):
+    return float(np.linalg.norm(got[1:4] - want[1:4]) / np.linalg.norm(want[1:4]))
