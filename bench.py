@@ -7,7 +7,7 @@ random solenoidal initial field (|k| <= 8, rms |u| = 0.02, seed 9160).  One
 launch).  Prints ONE JSON line.
 
   python bench.py [--steps K] [--warmup W] [--lattice 19|27]
-                  [--storage f32|f64|f16s|bf16s] [--n 512] [--variants]
+                  [--storage f32|f64|f16s|bf16s] [--n 512] [--no-variants]
                   [--no-cpu-baseline] [--copy-probe]
 """
 import argparse
@@ -23,12 +23,17 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS + % HBM roofline, D3Q19 512^3 FP32 vs 16-bit moments; adjoint MLUPS"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, AMD published peak
 BYTES_PER_VALUE = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
-KERNEL_SRC = os.path.join(ROOT, "paper_2609_09160_amd", "csrc", "step_kernel.hpp")
+CSRC = os.path.join(ROOT, "paper_2609_09160_amd", "csrc")
+KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("step_kernel.hpp", "lattice.hpp", "step_f32.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_d3q19_f32_512.txt")
 
 
 def kernel_hash():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the sources the FP32 step kernel is compiled from."""
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic(n_sites):
@@ -94,24 +99,33 @@ def run_gpu(n, lattice, storage, steps, warmup, m0=None, launch=(0, 0)):
             "hbm_frac": gbs / HBM_PEAK_GBS, "finite": bool(all(abs(v) < 1e300 for v in red))}
 
 
-def copy_ceiling(nbytes=4 << 30, reps=20):
-    """Device-to-device copy (torch's copy kernel) of nbytes: GB/s counting
-    read + write."""
+def stream_ceiling(n=512 ** 3, nplanes=10, reps=5):
+    """The library's plain stream copy (same memory instruction forms as the
+    step) of nplanes x n floats: GB/s counting read + write.  Also the number
+    of bytes one launch moves, for counter calibration."""
+    import ctypes
     import torch
-    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    from paper_2609_09160_amd import _lib
+    lib = _lib.load()
+    a = torch.ones(nplanes * n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    b.copy_(a)
+    stream = torch.cuda.current_stream()
+    args = (ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), n, nplanes,
+            ctypes.c_void_p(stream.cuda_stream))
+    _lib.check(lib.lbfast_stream_probe(*args))
     torch.cuda.synchronize()
     st, en = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    st.record()
+    st.record(stream)
     for _ in range(reps):
-        b.copy_(a)
-    en.record()
+        _lib.check(lib.lbfast_stream_probe(*args))
+    en.record(stream)
     torch.cuda.synchronize()
     ms = st.elapsed_time(en) / reps
+    assert torch.equal(a[:1024], b[:1024])
     del a, b
     torch.cuda.empty_cache()
-    return 2 * nbytes / (ms * 1e-3) / 1e9, ms
+    nbytes = 2 * 4 * nplanes * n
+    return nbytes / (ms * 1e-3) / 1e9, ms, nbytes
 
 
 def cpu_baseline(lattice, budget_s=15.0):
@@ -147,13 +161,13 @@ def main():
     ap.add_argument("--lattice", type=int, default=19, choices=(19, 27))
     ap.add_argument("--storage", default="f32", choices=tuple(BYTES_PER_VALUE))
     ap.add_argument("--n", type=int, default=512)
-    ap.add_argument("--variants", action="store_true",
-                    help="also time D3Q27, FP64 and 16-bit storage (short runs)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the short runs of D3Q27, FP64 and 16-bit storage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile-rows", type=int, default=0, help="launch override (0 = default)")
     ap.add_argument("--z-chunk", type=int, default=0, help="launch override (0 = default)")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="only time a plain device copy (counter calibration)")
+                    help="only run the library's stream copy (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -169,8 +183,9 @@ def main():
         sys.exit(1)
 
     if args.copy_probe:
-        gbs, ms = copy_ceiling()
-        print(json.dumps({"copy_GBs": round(gbs, 1), "ms": round(ms, 4), "bytes": 4 << 30}))
+        gbs, ms, nbytes = stream_ceiling()
+        print(json.dumps({"stream_GBs": round(gbs, 1), "ms": round(ms, 4),
+                          "bytes_read": nbytes // 2, "bytes_written": nbytes // 2}))
         return
 
     from paper_2609_09160_amd import _lib
@@ -210,7 +225,10 @@ def main():
                      "traffic": traffic,
                      "bytes_per_lup_algorithmic": bpl},
     }
-    if args.variants:
+    gbs, _, _ = stream_ceiling()
+    out["roofline"]["measured_stream_GBs"] = round(gbs, 1)
+    out["roofline"]["frac_of_measured_stream"] = round(achieved / gbs, 4)
+    if not args.no_variants:
         var = {}
         for lat, st in ((27, "f32"), (19, "f16s"), (19, "bf16s"), (27, "f16s"), (19, "f64")):
             if (lat, st) == (args.lattice, args.storage):
@@ -218,9 +236,8 @@ def main():
             r = run_gpu(n, lat, st, max(20, args.steps // 4), 5)
             var[f"d3q{lat}_{st}"] = {"mlups": round(r["mlups"], 1),
                                      "ms_per_step": round(r["ms_per_step"], 5),
+                                     "algorithmic_GBs": round(r["algorithmic_GBs"], 1),
                                      "hbm_frac": round(r["hbm_frac"], 4)}
-        gbs, _ = copy_ceiling()
-        var["device_copy_GBs"] = round(gbs, 1)
         out["variants"] = var
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         out["cpu_baseline"] = cpu_baseline(args.lattice)

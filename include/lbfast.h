@@ -145,6 +145,13 @@ int lbfast_get_scales(lbfast_t h, float out[10]);
  * reproducible from run to run. */
 int lbfast_set_launch(lbfast_t h, int tile_rows, int z_chunk);
 
+/* Measurement utility, not part of the method: copy `nplanes` planes of `n`
+ * floats from src to dst (device pointers, n * 4 < 2^32) on `stream`, using
+ * the same memory instruction forms as the step (dword buffer loads,
+ * non-temporal dword buffer stores).  A copy of known size, used to calibrate
+ * hardware traffic counters against the step. */
+int lbfast_stream_probe(const void* src, void* dst, int64_t n, int nplanes, void* stream);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char* lbfast_last_error(void);
 

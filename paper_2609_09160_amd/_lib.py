@@ -41,14 +41,16 @@ _lib = None
 
 
 def load():
-    """Load liblbfast.so; raises if it has not been built."""
+    """Load liblbfast.so (or the file named by LBFAST_LIB, for comparing
+    builds); raises if it has not been built."""
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+    path = os.environ.get("LBFAST_LIB") or LIB_PATH
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build the HIP library first "
                           "(python -m paper_2609_09160_amd.build)")
-    lib = ctypes.CDLL(LIB_PATH)
+    lib = ctypes.CDLL(path)
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     P = ctypes.POINTER(LbfastParams)
     sig = {
@@ -66,6 +68,7 @@ def load():
         "lbfast_get_scales": ([vp, ctypes.POINTER(ctypes.c_float)], i32),
         "lbfast_set_launch": ([vp, i32, i32], i32),
         "lbfast_last_error": ([], ctypes.c_char_p),
+        "lbfast_stream_probe": ([vp, vp, i64, i32, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -20,7 +20,7 @@ ARCH = os.environ.get("LBFAST_ARCH", "gfx950")
 SOURCES = ["step_f64.hip", "step_f32.hip", "step_f16s.hip", "step_bf16s.hip", "aux.hip",
            "lbfast.cpp"]
 
-COMMON = ["-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
+COMMON = ["-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]
 
@@ -32,10 +32,10 @@ def _hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src, verbose):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+def _compile(src, verbose, flags, build_dir, csrc):
+    obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [_hipcc()] + COMMON + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [_hipcc()] + flags + ["-I", csrc] + lang + ["-c", os.path.join(csrc, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -48,17 +48,26 @@ def _compile(src, verbose):
     return obj
 
 
-def build(verbose: bool = False, jobs: int = None) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, jobs: int = None, out: str = None, defines=(),
+          csrc: str = None) -> str:
+    """Compile every translation unit and link `out` (default: liblbfast.so
+    next to this file).  `defines` adds -D flags and `csrc` replaces the source
+    directory (tuning experiments build elsewhere)."""
+    lib = out or LIB
+    csrc = csrc or CSRC
+    flags = [f for f in COMMON if f != CSRC] + [f"-D{d}" for d in defines]
+    build_dir = os.path.join(os.path.dirname(lib), "_build_" + os.path.basename(lib)) \
+        if out else BUILD
+    os.makedirs(build_dir, exist_ok=True)
     jobs = jobs or min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
-    cmd = [_hipcc(), "-shared", f"--offload-arch={ARCH}", "-o", LIB + ".tmp"] + objs
+        objs = list(ex.map(lambda s: _compile(s, verbose, flags, build_dir, csrc), SOURCES))
+    cmd = [_hipcc(), "-shared", f"--offload-arch={ARCH}", "-o", lib + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -135,6 +135,22 @@ __global__ void reduce_final_kernel(const double* __restrict__ partials, int npa
   if (threadIdx.x < 5) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
+// plane-by-plane copy with the step's memory-instruction forms (dword buffer
+// loads, non-temporal dword buffer stores, one element per lane)
+__global__ void stream_probe_kernel(const float* __restrict__ src, float* __restrict__ dst,
+                                    int64_t n, int nplanes) {
+  const uint32_t bytes = static_cast<uint32_t>(n * sizeof(float));
+  for (int k = 0; k < nplanes; ++k) {
+    const auto rs = plane_rsrc(src + k * n, bytes);
+    const auto rd = plane_rsrc(dst + k * n, bytes);
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kThreads) {
+      const uint32_t off = static_cast<uint32_t>(i * sizeof(float));
+      buf_store_nt<float>(buf_load<float>(rs, off), rd, off);
+    }
+  }
+}
+
 Scales to_scales(const float* p) {
   Scales s;
   for (int k = 0; k < 10; ++k) s.v[k] = p[k];
@@ -183,6 +199,13 @@ hipError_t reduce_st(const void* buf, int64_t N, const float* scale, double* par
 }
 
 }  // namespace
+
+hipError_t launch_stream_probe(const void* src, void* dst, int64_t n, int nplanes,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(stream_probe_kernel, dim3(8192), dim3(kThreads), 0, s,
+                     static_cast<const float*>(src), static_cast<float*>(dst), n, nplanes);
+  return hipGetLastError();
+}
 
 hipError_t launch_encode(int storage, int user_dtype, const void* user, void* buf, int64_t N,
                          int64_t p0, int64_t np, const float* inv_scale, hipStream_t s) {

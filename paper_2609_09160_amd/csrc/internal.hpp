@@ -29,6 +29,11 @@ constexpr int kTileRowsSupported[] = {4, 6, 8, 14};
 hipError_t launch_step(int Q, int storage, int tile_rows, bool walls_y, const StepArgs& a,
                        hipStream_t stream);
 
+// copy nplanes planes of n floats (n * 4 < 2^32) with the step's memory
+// instruction forms
+hipError_t launch_stream_probe(const void* src, void* dst, int64_t n, int nplanes,
+                               hipStream_t stream);
+
 // user array (F64 or F32, 10 planes) -> storage buffer
 hipError_t launch_encode(int storage, int user_dtype, const void* user, void* buf, int64_t N,
                          int64_t plane_offset, int64_t nplanes, const float* inv_scale,

@@ -141,6 +141,7 @@ struct Storage<kF64> {
   using C = double;
   static __device__ __forceinline__ C load(const T* p, int64_t i, float) { return p[i]; }
   static __device__ __forceinline__ C decode(T q, float) { return q; }
+  static __device__ __forceinline__ T encode(C v, float) { return v; }
   static __device__ __forceinline__ void store(T* p, int64_t i, C v, float) {
     __builtin_nontemporal_store(v, p + i);
   }
@@ -155,6 +156,7 @@ struct Storage<kF32> {
   using C = float;
   static __device__ __forceinline__ C load(const T* p, int64_t i, float) { return p[i]; }
   static __device__ __forceinline__ C decode(T q, float) { return q; }
+  static __device__ __forceinline__ T encode(C v, float) { return v; }
   static __device__ __forceinline__ void store(T* p, int64_t i, C v, float) {
     __builtin_nontemporal_store(v, p + i);
   }
@@ -190,6 +192,7 @@ struct Storage<kF16S> {
     return f16_bits_to_f32(p[i]) * s;
   }
   static __device__ __forceinline__ C decode(T q, float s) { return f16_bits_to_f32(q) * s; }
+  static __device__ __forceinline__ T encode(C v, float inv_s) { return f32_to_f16_bits(v * inv_s); }
   static __device__ __forceinline__ void store(T* p, int64_t i, C v, float inv_s) {
     __builtin_nontemporal_store(f32_to_f16_bits(v * inv_s), p + i);
   }
@@ -206,6 +209,7 @@ struct Storage<kBF16S> {
     return bf16_bits_to_f32(p[i]) * s;
   }
   static __device__ __forceinline__ C decode(T q, float s) { return bf16_bits_to_f32(q) * s; }
+  static __device__ __forceinline__ T encode(C v, float inv_s) { return f32_to_bf16_bits(v * inv_s); }
   static __device__ __forceinline__ void store(T* p, int64_t i, C v, float inv_s) {
     __builtin_nontemporal_store(f32_to_bf16_bits(v * inv_s), p + i);
   }

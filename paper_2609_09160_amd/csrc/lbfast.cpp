@@ -187,6 +187,17 @@ size_t lbfast_buffer_bytes(const lbfast_params* p) {
 
 const char* lbfast_last_error(void) { return g_err.c_str(); }
 
+int lbfast_stream_probe(const void* src, void* dst, int64_t n, int nplanes, void* stream) {
+  g_err.clear();
+  if (!src || !dst) return fail(LBF_E_ARG, "null buffer");
+  if (n < 1 || static_cast<double>(n) * 4.0 >= 4294967296.0)
+    return fail(LBF_E_ARG, "n must be in [1, 2^30)");
+  if (nplanes < 1) return fail(LBF_E_ARG, "nplanes must be >= 1");
+  hipError_t e = lbf::launch_stream_probe(src, dst, n, nplanes, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "stream probe");
+  return LBF_OK;
+}
+
 int lbfast_create(const lbfast_params* p, void* stream, void* buf0, void* buf1, lbfast_t* out) {
   g_err.clear();
   if (!out) return fail(LBF_E_ARG, "out is NULL");

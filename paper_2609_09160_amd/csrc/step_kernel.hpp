@@ -36,6 +36,10 @@
 //     of tiles, y-neighbours first: concurrently running tiles share halo rows.
 #pragma once
 
+#ifndef LBF_PREFETCH_DEPTH
+#define LBF_PREFETCH_DEPTH 1
+#endif
+
 #include "internal.hpp"
 #include "lattice.hpp"
 
@@ -206,14 +210,14 @@ __global__ void __launch_bounds__(64 * (TY + 2)) step_kernel(const StepArgs a) {
   // the force field has the compute type; its byte offset scales accordingly
   constexpr uint32_t kFscale = sizeof(C) / sizeof(T);
   const uint32_t plane_bytes = static_cast<uint32_t>(plane * sizeof(T));
-  // plane index for zs in [-1, nz + 2] (zs is uniform: scalar arithmetic)
-  auto zwrap = [&](int zs) {
+  // periodic plane index for zs >= -1 (zs is uniform: scalar arithmetic;
+  // planes past the end of a padded chunk are fetched but never used)
+  auto zwrap = [&](int zs) __attribute__((always_inline)) {
     zs = zs < 0 ? zs + nz : zs;
     zs = zs >= nz ? zs - nz : zs;
-    zs = zs >= nz ? zs - nz : zs;
-    return zs >= nz ? 0 : zs;  // only for nz <= 2, planes beyond the chunk
+    return zs >= nz ? zs % nz : zs;
   };
-  auto fetch = [&](const int zs, const uint32_t off, Raw& r) {
+  auto fetch = [&](const int zs, const uint32_t off, Raw& r) __attribute__((always_inline)) {
     const int64_t pb = static_cast<int64_t>(zwrap(zs)) * plane;
 #pragma unroll
     for (int k = 0; k < 10; ++k)
@@ -224,7 +228,7 @@ __global__ void __launch_bounds__(64 * (TY + 2)) step_kernel(const StepArgs a) {
         r.F[k] = buf_load<C>(plane_rsrc(Ff + (k * N + pb), plane_bytes * kFscale), off * kFscale);
     }
   };
-  auto collide = [&](const Raw& r, C g[Q], C Fo[3]) {
+  auto collide = [&](const Raw& r, C g[Q], C Fo[3]) __attribute__((always_inline)) {
     C m[10];
 #pragma unroll
     for (int k = 0; k < 10; ++k) m[k] = S::decode(r.m[k], a.scale[k]);
@@ -239,7 +243,7 @@ __global__ void __launch_bounds__(64 * (TY + 2)) step_kernel(const StepArgs a) {
     }
     source_pops<Q, C>(m, Fo[0], Fo[1], Fo[2], omega, g);
   };
-  auto stage = [&](const C g[Q], const int row, const int col) {
+  auto stage = [&](const C g[Q], const int row, const int col) __attribute__((always_inline)) {
     static_for<NP>([&](auto I) {
       constexpr int i = decltype(I)::value;
       lds[i][row][col] = g[i];
@@ -248,7 +252,7 @@ __global__ void __launch_bounds__(64 * (TY + 2)) step_kernel(const StepArgs a) {
   // population i arriving at this thread's destination from the LDS plane;
   // on a wall row the ones that would come from beyond the wall are dropped
   // here and replaced by the reflections added in body_interior
-  auto pulled = [&](auto I) -> C {
+  auto pulled = [&](auto I) __attribute__((always_inline)) -> C {
     constexpr int i = decltype(I)::value;
     C v = lds[i][wv - L::cy(i)][lane + 1 - L::cx(i)];
     if constexpr (WALLY && L::cy(i) == 1) v = wall_lo ? C(0) : v;
@@ -263,10 +267,10 @@ __global__ void __launch_bounds__(64 * (TY + 2)) step_kernel(const StepArgs a) {
   // rn receives the next plane's (one plane of latency hiding).
   constexpr int NU = (Q == 19) ? 5 : 9;  // populations with c_z = +1
   auto body_interior = [&](const int zs, Sums<C>& acc, C (&up)[NU], C (&Fd)[3], Raw& rc,
-                           Raw& rn) {
-    // unconditional (the last plane of a chunk fetches one unused plane): a
+                           Raw& rn, const int ahead) __attribute__((always_inline)) {
+    // unconditional (the last planes of a chunk fetch unused planes): a
     // conditional fetch makes the wait-count merge stall on the fresh loads
-    fetch(zs + 1, off_s, rn);
+    fetch(zs + ahead, off_s, rn);
     C g[Q], Fs[3];
     collide(rc, g, Fs);
     stage(g, wv, lane + 1);
@@ -283,13 +287,14 @@ __global__ void __launch_bounds__(64 * (TY + 2)) step_kernel(const StepArgs a) {
     });
     {
       // Every iteration issues the same ten stores (uniform memory-op counts
-      // keep the wait counters precise); lanes with nothing to store -- the
-      // plane before the chunk, ragged tails -- use an offset at the end of
-      // the plane, which the buffer range check discards.
+      // keep the wait counters precise); lanes with nothing to store -- planes
+      // outside the chunk, ragged tails -- use an offset at the end of the
+      // plane, which the buffer range check discards.
       C out[10];
       finalize<Q, C>(acc, Fd[0], Fd[1], Fd[2], out);
-      const int64_t pb = static_cast<int64_t>(zs >= z0 + 1 ? zs - 1 : z0) * plane;
-      const uint32_t off = (store_ok && zs - 1 >= z0) ? off_d : plane_bytes;
+      const bool live = zs - 1 >= z0 && zs - 1 < z1;
+      const int64_t pb = static_cast<int64_t>(live ? zs - 1 : z0) * plane;
+      const uint32_t off = (store_ok && live) ? off_d : plane_bytes;
 #pragma unroll
       for (int k = 0; k < 10; ++k)
         S::store_at(plane_rsrc(dst + (k * N + pb), plane_bytes), off, out[k], a.inv_scale[k]);
@@ -354,7 +359,7 @@ __global__ void __launch_bounds__(64 * (TY + 2)) step_kernel(const StepArgs a) {
   const int hwave = (wv == 0) ? 0 : 1;
   // lanes without an x-halo site fetch at the plane end: zeros, no fault
   const uint32_t off_hf = do_halo ? off_h : plane_bytes;
-  auto col_to_buf = [&](const Raw& r) {
+  auto col_to_buf = [&](const Raw& r) __attribute__((always_inline)) {
     C g[Q], Fs[3];
     collide(r, g, Fs);
     if (do_halo)
@@ -363,8 +368,10 @@ __global__ void __launch_bounds__(64 * (TY + 2)) step_kernel(const StepArgs a) {
         colbuf[i][hwave][lane] = g[i];
       });
   };
-  auto body_halo = [&](const int zs, Raw& rc, Raw& rn, Raw& hc, Raw& hn) {
-    fetch(zs + 1, off_s, rn);
+  // rc: this plane's row site, rn: receives plane zs+ahead; hc: the column
+  // site of plane zs+1, refilled after use with plane zs+1+U
+  auto body_halo = [&](const int zs, Raw& rc, Raw& rn, Raw& hc, const int ahead) __attribute__((always_inline)) {
+    fetch(zs + ahead, off_s, rn);
     if (do_halo)
       static_for<NP>([&](auto I) {
         constexpr int i = decltype(I)::value;
@@ -376,14 +383,20 @@ __global__ void __launch_bounds__(64 * (TY + 2)) step_kernel(const StepArgs a) {
       stage(g, wv, lane + 1);
     }
     __syncthreads();
-    fetch(zs + 2, off_hf, hn);
     col_to_buf(hc);
+    fetch(zs + 1 + (ahead + 1), off_hf, hc);
     __syncthreads();
   };
 
   // The role is uniform per wave; the two roles run separate loops so that
-  // their loop-carried registers never coexist.  Both execute exactly two
-  // barriers per source plane z0-1 .. z1.
+  // their loop-carried registers never coexist.  Both run the same padded
+  // number of source planes (z0-1 .. z1, rounded up to a multiple of the
+  // unroll U) with exactly two barriers each; padded planes compute values
+  // that are never stored.  Every path through a loop trip issues the same
+  // memory operations, which keeps the compiler's wait counts exact.
+  constexpr int PF = LBF_PREFETCH_DEPTH;  // planes of moments in flight
+  constexpr int U = PF + 1;               // rotating raw buffers = unroll
+  const int trips = ((z1 - z0 + 2) + U - 1) / U;
   const bool interior_wave = __builtin_amdgcn_readfirstlane(static_cast<int>(interior)) != 0;
   if (interior_wave) {
     Sums<C> acc;
@@ -391,26 +404,32 @@ __global__ void __launch_bounds__(64 * (TY + 2)) step_kernel(const StepArgs a) {
     C up[NU], Fd[3] = {C(0), C(0), C(0)};
 #pragma unroll
     for (int u = 0; u < NU; ++u) up[u] = C(0);
-    // not unrolled: the prefetched registers are copied at the end of the
-    // iteration, so the only wait on them comes a full plane after issue
-    Raw rc, rn;
-    fetch(z0 - 1, off_s, rc);
+    Raw rr[U];
+    static_for<PF>([&](auto J) { fetch(z0 - 1 + J, off_s, rr[J]); });
 #pragma unroll 1
-    for (int zs = z0 - 1; zs <= z1; ++zs) {
-      body_interior(zs, acc, up, Fd, rc, rn);
-      rc = rn;
+    for (int t = 0; t < trips; ++t) {
+      const int zb = z0 - 1 + t * U;
+      static_for<U>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        body_interior(zb + k, acc, up, Fd, rr[k], rr[(k + PF) % U], PF);
+      });
     }
   } else {
-    Raw rc, rn, hc, hn;
-    fetch(z0 - 1, off_hf, hc);
-    col_to_buf(hc);  // columns of the first source plane
-    fetch(z0, off_hf, hc);
-    fetch(z0 - 1, off_s, rc);
+    Raw rr[U], hh[U];
+    {
+      Raw first;
+      fetch(z0 - 1, off_hf, first);
+      col_to_buf(first);  // columns of the first source plane
+    }
+    static_for<U>([&](auto J) { fetch(z0 + J, off_hf, hh[J]); });
+    static_for<PF>([&](auto J) { fetch(z0 - 1 + J, off_s, rr[J]); });
 #pragma unroll 1
-    for (int zs = z0 - 1; zs <= z1; ++zs) {
-      body_halo(zs, rc, rn, hc, hn);
-      rc = rn;
-      hc = hn;
+    for (int t = 0; t < trips; ++t) {
+      const int zb = z0 - 1 + t * U;
+      static_for<U>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        body_halo(zb + k, rr[k], rr[(k + PF) % U], hh[k], PF);
+      });
     }
   }
 }
