@@ -128,7 +128,7 @@ def stream_ceiling(n=512 ** 3, nplanes=10, reps=5):
     return nbytes / (ms * 1e-3) / 1e9, ms, nbytes
 
 
-def cpu_baseline(lattice, budget_s=15.0):
+def cpu_baseline(lattice, budget_s=20.0):
     """The FP64 CPU oracle on the host cores, bounded sample of the workload."""
     import numpy as np
     import oracle
@@ -142,7 +142,7 @@ def cpu_baseline(lattice, budget_s=15.0):
     t0 = time.perf_counter()
     o.step(1)
     one = time.perf_counter() - t0
-    k = max(1, min(40, int(budget_s / max(one, 1e-3))))
+    k = max(1, min(1000, int(budget_s / max(one, 1e-3))))
     t0 = time.perf_counter()
     o.step(k)
     dt = time.perf_counter() - t0

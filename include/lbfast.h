@@ -68,7 +68,9 @@ enum { LBF_D3Q19 = 19, LBF_D3Q27 = 27 };
 
 /* element types: storage of the moment planes, and dtype of user arrays.
  * F16S/BF16S = 16-bit storage of v/s_m with a power-of-two scale s_m per
- * moment plane; arithmetic is FP32 (only valid as `storage`). */
+ * moment plane, arithmetic in FP32 (only valid as `storage`).  In 16-bit
+ * storage the second-order planes hold the deviation a2 - u u (u as stored),
+ * p* and u are deviations already; the ABI always exchanges the total a2. */
 enum { LBF_F64 = 0, LBF_F32 = 1, LBF_F16S = 2, LBF_BF16S = 3 };
 
 /* boundary per axis: periodic, or stationary halfway bounce-back walls at
@@ -87,7 +89,9 @@ typedef struct lbfast_params {
                            ignored while a force field is set */
   float scale[10];      /* 16-bit storage only: power-of-two scale per moment
                            plane; 0 = choose at the first set_moments as the
-                           power of two that maps 2*max|v| near 2^15 (FP16) */
+                           power of two that maps 2*max|v| (v the plane's
+                           total value) just below 2^15; a state at rest has
+                           no magnitude to go by: pass scales explicitly */
   int32_t reserved[8];  /* must be zero */
 } lbfast_params;
 

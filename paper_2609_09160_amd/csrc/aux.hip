@@ -38,41 +38,75 @@ int grid_for(int64_t n) {
   return static_cast<int>(b < 8192 ? (b < 1 ? 1 : b) : 8192);
 }
 
+// velocity component c of site i as it reads back from storage: the user's
+// value rounded to the storage format (deviation planes are relative to it)
 template <int ST, typename U>
-__global__ void encode_kernel(const U* __restrict__ user, typename Storage<ST>::T* __restrict__ buf,
-                              int64_t N, int64_t p0, Scales inv) {
-  const int k = static_cast<int>(blockIdx.y);
-  const int64_t base = (p0 + k) * N;
-  const U* u = user + static_cast<int64_t>(k) * N;
+__device__ __forceinline__ float stored_u(const U* u, int64_t i, float inv, float s) {
+  using S = Storage<ST>;
+  return static_cast<float>(S::decode(S::encode(static_cast<typename S::C>(u[i]), inv), s));
+}
+
+// user plane k (F64/F32) -> storage plane k; for deviation storage the planes
+// k >= 4 hold a2 - u u with u rounded as stored (u0..u2: the user's u planes)
+template <int ST, typename U>
+__global__ void encode_kernel(const U* __restrict__ user, const U* __restrict__ u0,
+                              const U* __restrict__ u1, const U* __restrict__ u2,
+                              typename Storage<ST>::T* __restrict__ buf, int64_t N, int k,
+                              Scales inv, Scales fwd) {
+  using S = Storage<ST>;
+  using C = typename S::C;
+  const int64_t base = static_cast<int64_t>(k) * N;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < N;
        i += static_cast<int64_t>(gridDim.x) * kThreads) {
-    using C = typename Storage<ST>::C;
-    const C v = static_cast<C>(u[i]);
-    Storage<ST>::store(buf, base + i, v, inv.v[p0 + k]);
+    C v = static_cast<C>(user[i]);
+    if constexpr (S::kNeq) {
+      if (k >= 4) {
+        const U* ua = a2_a(k) == 0 ? u0 : (a2_a(k) == 1 ? u1 : u2);
+        const U* ub = a2_b(k) == 0 ? u0 : (a2_b(k) == 1 ? u1 : u2);
+        v -= static_cast<C>(stored_u<ST>(ua, i, inv.v[1 + a2_a(k)], fwd.v[1 + a2_a(k)]) *
+                            stored_u<ST>(ub, i, inv.v[1 + a2_b(k)], fwd.v[1 + a2_b(k)]));
+      }
+    }
+    S::store(buf, base + i, v, inv.v[k]);
   }
 }
 
+// storage plane k -> user plane k (total a2 for deviation storage)
 template <int ST, typename U>
 __global__ void decode_kernel(const typename Storage<ST>::T* __restrict__ buf, U* __restrict__ user,
-                              int64_t N, int64_t p0, Scales s) {
-  const int k = static_cast<int>(blockIdx.y);
-  const int64_t base = (p0 + k) * N;
-  U* u = user + static_cast<int64_t>(k) * N;
+                              int64_t N, int k, Scales s) {
+  using S = Storage<ST>;
+  const int64_t base = static_cast<int64_t>(k) * N;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < N;
        i += static_cast<int64_t>(gridDim.x) * kThreads) {
-    u[i] = static_cast<U>(Storage<ST>::load(buf, base + i, s.v[p0 + k]));
+    auto v = S::load(buf, base + i, s.v[k]);
+    if constexpr (S::kNeq) {
+      if (k >= 4)
+        v += S::load(buf, (1 + a2_a(k)) * N + i, s.v[1 + a2_a(k)]) *
+             S::load(buf, (1 + a2_b(k)) * N + i, s.v[1 + a2_b(k)]);
+    }
+    user[i] = static_cast<U>(v);
   }
 }
 
-template <typename U>
-__global__ void maxabs_kernel(const U* __restrict__ user, int64_t N, int64_t p0,
-                              unsigned* __restrict__ out_bits) {
-  const int k = static_cast<int>(blockIdx.y);
-  const U* u = user + static_cast<int64_t>(k) * N;
+// max |value stored in plane k| over a user plane (deviation for k >= 4 when
+// `dev`), into out_bits[k] (float bits; must start at zero)
+template <int ST, typename U>
+__global__ void maxabs_kernel(const U* __restrict__ user, const U* __restrict__ u0,
+                              const U* __restrict__ u1, const U* __restrict__ u2, int64_t N, int k,
+                              int dev, Scales inv, Scales fwd, unsigned* __restrict__ out_bits) {
   float m = 0.0f;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < N;
        i += static_cast<int64_t>(gridDim.x) * kThreads) {
-    const float v = fabsf(static_cast<float>(u[i]));
+    float v = static_cast<float>(user[i]);
+    if (dev && k >= 4) {
+      const U* ua = a2_a(k) == 0 ? u0 : (a2_a(k) == 1 ? u1 : u2);
+      const U* ub = a2_b(k) == 0 ? u0 : (a2_b(k) == 1 ? u1 : u2);
+      v = static_cast<float>(static_cast<double>(user[i]) -
+                             static_cast<double>(stored_u<ST>(ua, i, inv.v[1 + a2_a(k)], fwd.v[1 + a2_a(k)])) *
+                             stored_u<ST>(ub, i, inv.v[1 + a2_b(k)], fwd.v[1 + a2_b(k)]));
+    }
+    v = fabsf(v);
     m = v > m ? v : m;  // NaN never wins; an all-NaN plane keeps scale 1
   }
   __shared__ float sh[kThreads];
@@ -84,7 +118,7 @@ __global__ void maxabs_kernel(const U* __restrict__ user, int64_t N, int64_t p0,
     __syncthreads();
   }
   // non-negative float bits order like unsigned integers
-  if (threadIdx.x == 0) atomicMax(out_bits + p0 + k, __float_as_uint(sh[0]));
+  if (threadIdx.x == 0) atomicMax(out_bits + k, __float_as_uint(sh[0]));
 }
 
 template <int ST>
@@ -158,32 +192,58 @@ Scales to_scales(const float* p) {
 }
 
 template <int ST>
-hipError_t encode_st(int user_dtype, const void* user, void* buf, int64_t N, int64_t p0,
-                     int64_t np, const float* inv, hipStream_t st) {
+hipError_t encode_st(int user_dtype, const void* plane, const void* const u[3], void* buf,
+                     int64_t N, int k, const float* inv, const float* fwd, hipStream_t st) {
   using T = typename Storage<ST>::T;
-  const dim3 grid(grid_for(N), static_cast<unsigned>(np));
+  const dim3 grid(grid_for(N));
   if (user_dtype == kF64)
     hipLaunchKernelGGL((encode_kernel<ST, double>), grid, dim3(kThreads), 0, st,
-                       static_cast<const double*>(user), static_cast<T*>(buf), N, p0, to_scales(inv));
+                       static_cast<const double*>(plane), static_cast<const double*>(u[0]),
+                       static_cast<const double*>(u[1]), static_cast<const double*>(u[2]),
+                       static_cast<T*>(buf), N, k, to_scales(inv), to_scales(fwd));
   else
     hipLaunchKernelGGL((encode_kernel<ST, float>), grid, dim3(kThreads), 0, st,
-                       static_cast<const float*>(user), static_cast<T*>(buf), N, p0, to_scales(inv));
+                       static_cast<const float*>(plane), static_cast<const float*>(u[0]),
+                       static_cast<const float*>(u[1]), static_cast<const float*>(u[2]),
+                       static_cast<T*>(buf), N, k, to_scales(inv), to_scales(fwd));
   return hipGetLastError();
 }
 
 template <int ST>
-hipError_t decode_st(int user_dtype, const void* buf, void* user, int64_t N, int64_t p0,
-                     int64_t np, const float* scale, hipStream_t st) {
+hipError_t decode_st(int user_dtype, const void* buf, void* plane, int64_t N, int k,
+                     const float* scale, hipStream_t st) {
   using T = typename Storage<ST>::T;
-  const dim3 grid(grid_for(N), static_cast<unsigned>(np));
+  const dim3 grid(grid_for(N));
   if (user_dtype == kF64)
     hipLaunchKernelGGL((decode_kernel<ST, double>), grid, dim3(kThreads), 0, st,
-                       static_cast<const T*>(buf), static_cast<double*>(user), N, p0,
+                       static_cast<const T*>(buf), static_cast<double*>(plane), N, k,
                        to_scales(scale));
   else
     hipLaunchKernelGGL((decode_kernel<ST, float>), grid, dim3(kThreads), 0, st,
-                       static_cast<const T*>(buf), static_cast<float*>(user), N, p0,
+                       static_cast<const T*>(buf), static_cast<float*>(plane), N, k,
                        to_scales(scale));
+  return hipGetLastError();
+}
+
+template <int ST>
+hipError_t maxabs_st(int user_dtype, const void* plane, const void* const u[3], int64_t N, int k,
+                     const float* inv, const float* fwd, unsigned* out_bits, hipStream_t st) {
+  const dim3 grid(grid_for(N));
+  // The scale of every plane follows the magnitude of the total value: the
+  // deviation a2 - u u of a state at equilibrium is ~0, and a scale sized on it
+  // would overflow once the flow builds its non-equilibrium stress; smaller
+  // deviations stay in the normal range of the 16-bit format.
+  const int dev = 0;
+  if (user_dtype == kF64)
+    hipLaunchKernelGGL((maxabs_kernel<ST, double>), grid, dim3(kThreads), 0, st,
+                       static_cast<const double*>(plane), static_cast<const double*>(u[0]),
+                       static_cast<const double*>(u[1]), static_cast<const double*>(u[2]), N, k,
+                       dev, to_scales(inv), to_scales(fwd), out_bits);
+  else
+    hipLaunchKernelGGL((maxabs_kernel<ST, float>), grid, dim3(kThreads), 0, st,
+                       static_cast<const float*>(plane), static_cast<const float*>(u[0]),
+                       static_cast<const float*>(u[1]), static_cast<const float*>(u[2]), N, k,
+                       dev, to_scales(inv), to_scales(fwd), out_bits);
   return hipGetLastError();
 }
 
@@ -207,38 +267,40 @@ hipError_t launch_stream_probe(const void* src, void* dst, int64_t n, int nplane
   return hipGetLastError();
 }
 
-hipError_t launch_encode(int storage, int user_dtype, const void* user, void* buf, int64_t N,
-                         int64_t p0, int64_t np, const float* inv_scale, hipStream_t s) {
+hipError_t launch_encode(int storage, int user_dtype, const void* plane, const void* const u[3],
+                         void* buf, int64_t N, int k, const float* inv_scale, const float* scale,
+                         hipStream_t s) {
   switch (storage) {
-    case kF64: return encode_st<kF64>(user_dtype, user, buf, N, p0, np, inv_scale, s);
-    case kF32: return encode_st<kF32>(user_dtype, user, buf, N, p0, np, inv_scale, s);
-    case kF16S: return encode_st<kF16S>(user_dtype, user, buf, N, p0, np, inv_scale, s);
-    case kBF16S: return encode_st<kBF16S>(user_dtype, user, buf, N, p0, np, inv_scale, s);
+    case kF64: return encode_st<kF64>(user_dtype, plane, u, buf, N, k, inv_scale, scale, s);
+    case kF32: return encode_st<kF32>(user_dtype, plane, u, buf, N, k, inv_scale, scale, s);
+    case kF16S: return encode_st<kF16S>(user_dtype, plane, u, buf, N, k, inv_scale, scale, s);
+    case kBF16S: return encode_st<kBF16S>(user_dtype, plane, u, buf, N, k, inv_scale, scale, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_decode(int storage, int user_dtype, const void* buf, void* user, int64_t N,
-                         int64_t p0, int64_t np, const float* scale, hipStream_t s) {
+hipError_t launch_decode(int storage, int user_dtype, const void* buf, void* plane, int64_t N,
+                         int k, const float* scale, hipStream_t s) {
   switch (storage) {
-    case kF64: return decode_st<kF64>(user_dtype, buf, user, N, p0, np, scale, s);
-    case kF32: return decode_st<kF32>(user_dtype, buf, user, N, p0, np, scale, s);
-    case kF16S: return decode_st<kF16S>(user_dtype, buf, user, N, p0, np, scale, s);
-    case kBF16S: return decode_st<kBF16S>(user_dtype, buf, user, N, p0, np, scale, s);
+    case kF64: return decode_st<kF64>(user_dtype, buf, plane, N, k, scale, s);
+    case kF32: return decode_st<kF32>(user_dtype, buf, plane, N, k, scale, s);
+    case kF16S: return decode_st<kF16S>(user_dtype, buf, plane, N, k, scale, s);
+    case kBF16S: return decode_st<kBF16S>(user_dtype, buf, plane, N, k, scale, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_maxabs(int user_dtype, const void* user, int64_t N, int64_t p0, int64_t np,
+hipError_t launch_maxabs(int storage, int user_dtype, const void* plane, const void* const u[3],
+                         int64_t N, int k, const float* inv_scale, const float* scale,
                          unsigned* out_bits, hipStream_t s) {
-  const dim3 grid(grid_for(N), static_cast<unsigned>(np));
-  if (user_dtype == kF64)
-    hipLaunchKernelGGL(maxabs_kernel<double>, grid, dim3(kThreads), 0, s,
-                       static_cast<const double*>(user), N, p0, out_bits);
-  else
-    hipLaunchKernelGGL(maxabs_kernel<float>, grid, dim3(kThreads), 0, s,
-                       static_cast<const float*>(user), N, p0, out_bits);
-  return hipGetLastError();
+  switch (storage) {
+    case kF64: return maxabs_st<kF64>(user_dtype, plane, u, N, k, inv_scale, scale, out_bits, s);
+    case kF32: return maxabs_st<kF32>(user_dtype, plane, u, N, k, inv_scale, scale, out_bits, s);
+    case kF16S: return maxabs_st<kF16S>(user_dtype, plane, u, N, k, inv_scale, scale, out_bits, s);
+    case kBF16S:
+      return maxabs_st<kBF16S>(user_dtype, plane, u, N, k, inv_scale, scale, out_bits, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_reduce(int storage, const void* buf, int64_t N, const float* scale,

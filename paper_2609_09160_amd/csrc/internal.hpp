@@ -34,18 +34,19 @@ hipError_t launch_step(int Q, int storage, int tile_rows, bool walls_y, const St
 hipError_t launch_stream_probe(const void* src, void* dst, int64_t n, int nplanes,
                                hipStream_t stream);
 
-// user array (F64 or F32, 10 planes) -> storage buffer
-hipError_t launch_encode(int storage, int user_dtype, const void* user, void* buf, int64_t N,
-                         int64_t plane_offset, int64_t nplanes, const float* inv_scale,
+// Conversions between user planes (F64 or F32, N values each) and plane k of
+// a storage buffer.  u[0..2] are the user's velocity planes (the deviation
+// storage of the second-order planes needs them); scale/inv_scale: the 10
+// per-plane storage scales.
+hipError_t launch_encode(int storage, int user_dtype, const void* plane, const void* const u[3],
+                         void* buf, int64_t N, int k, const float* inv_scale, const float* scale,
                          hipStream_t stream);
-// storage buffer -> user array
-hipError_t launch_decode(int storage, int user_dtype, const void* buf, void* user, int64_t N,
-                         int64_t plane_offset, int64_t nplanes, const float* scale,
-                         hipStream_t stream);
-// per-plane max |v| of a user array (10 planes) into out_bits[10] (float bits,
-// must be zeroed before)
-hipError_t launch_maxabs(int user_dtype, const void* user, int64_t N, int64_t plane_offset,
-                         int64_t nplanes, unsigned* out_bits, hipStream_t stream);
+hipError_t launch_decode(int storage, int user_dtype, const void* buf, void* plane, int64_t N,
+                         int k, const float* scale, hipStream_t stream);
+// max |stored value| of user plane k into out_bits[k] (float bits, zeroed before)
+hipError_t launch_maxabs(int storage, int user_dtype, const void* plane, const void* const u[3],
+                         int64_t N, int k, const float* inv_scale, const float* scale,
+                         unsigned* out_bits, hipStream_t stream);
 // FP64 sums [a0, a1x, a1y, a1z, 1/2 |a1|^2] of the state into out[5]
 // (partials: kReduceBlocks*5 doubles of scratch)
 constexpr int kReduceBlocks = 1024;

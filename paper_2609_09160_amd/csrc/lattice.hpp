@@ -135,10 +135,16 @@ __device__ __forceinline__ void buf_store_nt(V v, __amdgpu_buffer_rsrc_t r, uint
 
 template <int ST>
 struct Storage;
+// kNeq: the second-order planes hold the deviation a2 - u u (the
+// non-equilibrium stress, small) instead of the total a2 (about u u plus a much
+// smaller deviation), so 16-bit rounding does not wipe out the viscous stress.
+// The u used is the stored (rounded) velocity, so decoding is exact up to the
+// rounding of the deviation itself.
 template <>
 struct Storage<kF64> {
   using T = double;
   using C = double;
+  static constexpr bool kNeq = false;
   static __device__ __forceinline__ C load(const T* p, int64_t i, float) { return p[i]; }
   static __device__ __forceinline__ C decode(T q, float) { return q; }
   static __device__ __forceinline__ T encode(C v, float) { return v; }
@@ -154,6 +160,7 @@ template <>
 struct Storage<kF32> {
   using T = float;
   using C = float;
+  static constexpr bool kNeq = false;
   static __device__ __forceinline__ C load(const T* p, int64_t i, float) { return p[i]; }
   static __device__ __forceinline__ C decode(T q, float) { return q; }
   static __device__ __forceinline__ T encode(C v, float) { return v; }
@@ -188,6 +195,7 @@ template <>
 struct Storage<kF16S> {
   using T = uint16_t;
   using C = float;
+  static constexpr bool kNeq = true;
   static __device__ __forceinline__ C load(const T* p, int64_t i, float s) {
     return f16_bits_to_f32(p[i]) * s;
   }
@@ -205,6 +213,7 @@ template <>
 struct Storage<kBF16S> {
   using T = uint16_t;
   using C = float;
+  static constexpr bool kNeq = true;
   static __device__ __forceinline__ C load(const T* p, int64_t i, float s) {
     return bf16_bits_to_f32(p[i]) * s;
   }
@@ -218,6 +227,10 @@ struct Storage<kBF16S> {
     buf_store_nt<T>(f32_to_bf16_bits(v * inv_s), r, off);
   }
 };
+
+// index pairs (a, b) of the second-order planes 4..9: xx, yy, zz, xy, xz, yz
+__host__ __device__ constexpr int a2_a(int k) { return k <= 6 ? k - 4 : (k == 9 ? 1 : 0); }
+__host__ __device__ constexpr int a2_b(int k) { return k <= 6 ? k - 4 : (k == 7 ? 1 : 2); }
 
 // periodic index for v in [-n, 2n)
 __device__ __forceinline__ int wrap(int v, int n) {

@@ -289,62 +289,76 @@ int lbfast_set_moments(lbfast_t h, const void* m, int dtype, int on_device) {
   DeviceGuard g(h->device);
   const size_t ub = (dtype == LBF_F64) ? 8 : 4;
   const int64_t N = h->N;
+  const size_t pbytes = static_cast<size_t>(N) * ub;
   hipError_t e = hipSuccess;
-  void* staging = nullptr;
+  // Device input is read in place.  Host input goes through a device staging
+  // area: the three velocity planes (kept for the whole call, the deviation
+  // storage of the second-order planes needs them) and one plane at a time.
+  char* staging = nullptr;
   if (!on_device) {
-    e = hipMalloc(&staging, static_cast<size_t>(N) * ub);
+    e = hipMalloc(reinterpret_cast<void**>(&staging), 4 * pbytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return fail(LBF_E_NOMEM, "staging allocation failed");
     }
+    e = hipMemcpyAsync(staging, static_cast<const char*>(m) + pbytes, 3 * pbytes,
+                       hipMemcpyHostToDevice, h->stream);
   }
-  auto plane_src = [&](int k) -> const void* {
-    return static_cast<const char*>(m) + static_cast<size_t>(k) * N * ub;
+  const void* u[3];
+  for (int c = 0; c < 3; ++c)
+    u[c] = on_device ? static_cast<const char*>(m) + (1 + c) * pbytes
+                     : static_cast<const void*>(staging + c * pbytes);
+  // device pointer of user plane k (host planes are copied in first)
+  auto plane = [&](int k, hipError_t& err) -> const void* {
+    if (on_device) return static_cast<const char*>(m) + k * pbytes;
+    if (k >= 1 && k <= 3) return staging + (k - 1) * pbytes;
+    char* p = staging + 3 * pbytes;
+    err = hipMemcpyAsync(p, static_cast<const char*>(m) + k * pbytes, pbytes,
+                         hipMemcpyHostToDevice, h->stream);
+    return p;
   };
-  // automatic 16-bit scales: power of two placing 2*max|v| just below 2^15
+  // automatic 16-bit scales: the power of two placing 2*max|v| just below 2^15
+  // (v: the plane's total value, the deviation planes included)
   if (!h->scales_fixed) {
-    e = hipMemsetAsync(h->d_maxbits, 0, 16 * sizeof(unsigned), h->stream);
-    for (int k = 0; k < 10 && e == hipSuccess; ++k) {
-      const void* src = plane_src(k);
-      if (!on_device) {
-        e = hipMemcpyAsync(staging, src, N * ub, hipMemcpyHostToDevice, h->stream);
-        src = staging;
+    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+      const int k0 = pass == 0 ? 0 : 4, k1 = pass == 0 ? 4 : 10;
+      e = hipMemsetAsync(h->d_maxbits, 0, 16 * sizeof(unsigned), h->stream);
+      for (int k = k0; k < k1 && e == hipSuccess; ++k) {
+        const void* src = plane(k, e);
+        if (e == hipSuccess)
+          e = lbf::launch_maxabs(h->p.storage, dtype, src, u, N, k, h->inv_scale, h->scale,
+                                 h->d_maxbits, h->stream);
+        // the single plane slot of the staging area is reused: wait before the next copy
+        if (e == hipSuccess && !on_device) e = hipStreamSynchronize(h->stream);
       }
-      if (e == hipSuccess) e = lbf::launch_maxabs(dtype, src, N, k, 1, h->d_maxbits, h->stream);
-    }
-    unsigned bits[16];
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(bits, h->d_maxbits, sizeof bits, hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e == hipSuccess) {
-      for (int k = 0; k < 10; ++k) {
+      unsigned bits[16];
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(bits, h->d_maxbits, sizeof bits, hipMemcpyDeviceToHost, h->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+      if (e != hipSuccess) break;
+      for (int k = k0; k < k1; ++k) {
         if (h->p.scale[k] != 0.0f) continue;
         float mx;
         std::memcpy(&mx, &bits[k], sizeof mx);
-        float s = 1.0f;
+        float sc = 1.0f;
         if (mx > 0.0f && std::isfinite(mx)) {
           int ex;
-          std::frexp(2.0f * mx, &ex);        // 2*mx in [2^(ex-1), 2^ex)
-          s = std::ldexp(1.0f, ex - 15);     // 2*mx / s < 2^15
+          std::frexp(2.0f * mx, &ex);      // 2*mx in [2^(ex-1), 2^ex)
+          sc = std::ldexp(1.0f, ex - 15);  // 2*mx / sc < 2^15
         }
-        h->scale[k] = s;
-        h->inv_scale[k] = 1.0f / s;
+        h->scale[k] = sc;
+        h->inv_scale[k] = 1.0f / sc;
       }
-      h->scales_fixed = true;
     }
+    if (e == hipSuccess) h->scales_fixed = true;
   }
   void* dst = h->buf[h->cur];
-  if (e == hipSuccess) {
-    if (on_device) {
-      e = lbf::launch_encode(h->p.storage, dtype, m, dst, N, 0, 10, h->inv_scale, h->stream);
-    } else {
-      for (int k = 0; k < 10 && e == hipSuccess; ++k) {
-        e = hipMemcpyAsync(staging, plane_src(k), N * ub, hipMemcpyHostToDevice, h->stream);
-        if (e == hipSuccess)
-          e = lbf::launch_encode(h->p.storage, dtype, staging, dst, N, k, 1, h->inv_scale,
-                                 h->stream);
-      }
-    }
+  for (int k = 0; k < 10 && e == hipSuccess; ++k) {
+    const void* src = plane(k, e);
+    if (e == hipSuccess)
+      e = lbf::launch_encode(h->p.storage, dtype, src, u, dst, N, k, h->inv_scale, h->scale,
+                             h->stream);
+    if (e == hipSuccess && !on_device) e = hipStreamSynchronize(h->stream);
   }
   if (staging) {
     hipError_t e2 = hipStreamSynchronize(h->stream);
@@ -364,29 +378,27 @@ int lbfast_get_moments(lbfast_t h, void* m, int dtype, int on_device) {
   DeviceGuard g(h->device);
   const size_t ub = (dtype == LBF_F64) ? 8 : 4;
   const int64_t N = h->N;
+  const size_t pbytes = static_cast<size_t>(N) * ub;
   const void* src = h->buf[h->cur];
   hipError_t e = hipSuccess;
-  if (on_device) {
-    e = lbf::launch_decode(h->p.storage, dtype, src, m, N, 0, 10, h->scale, h->stream);
-  } else {
-    void* staging = nullptr;
-    e = hipMalloc(&staging, static_cast<size_t>(N) * ub);
+  void* staging = nullptr;
+  if (!on_device) {
+    e = hipMalloc(&staging, pbytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return fail(LBF_E_NOMEM, "staging allocation failed");
     }
-    for (int k = 0; k < 10 && e == hipSuccess; ++k) {
-      e = lbf::launch_decode(h->p.storage, dtype, src, staging, N, k, 1, h->scale, h->stream);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(static_cast<char*>(m) + static_cast<size_t>(k) * N * ub, staging,
-                           N * ub, hipMemcpyDeviceToHost, h->stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    }
-    hipError_t e2 = hipStreamSynchronize(h->stream);
-    if (e == hipSuccess) e = e2;
-    (void)hipFree(staging);
+  }
+  for (int k = 0; k < 10 && e == hipSuccess; ++k) {
+    void* dst = on_device ? static_cast<void*>(static_cast<char*>(m) + k * pbytes) : staging;
+    e = lbf::launch_decode(h->p.storage, dtype, src, dst, N, k, h->scale, h->stream);
+    if (e == hipSuccess && !on_device)
+      e = hipMemcpyAsync(static_cast<char*>(m) + k * pbytes, staging, pbytes,
+                         hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && !on_device) e = hipStreamSynchronize(h->stream);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (staging) (void)hipFree(staging);
   if (e != hipSuccess) return hip_fail(e, "get_moments");
   return LBF_OK;
 }

@@ -1,0 +1,394 @@
+// march.hpp -- the z-marching pull-stencil skeleton shared by the fused step
+// (step_kernel.hpp) and its discrete adjoint (adjoint_kernel.hpp).
+//
+// Both kernels have the same shape: every site evaluates Q values that travel
+// to its neighbours ("populations": value i leaves site y towards y + c_i),
+// every site gathers the Q values that arrive from y - c_i (periodic wrap, or
+// halfway bounce-back at the y walls: a value that would arrive from beyond a
+// wall is replaced by the opposite value leaving the site itself), and
+// projects them on the Hermite basis H0, H1, H2 (running sums s0, j, p).
+// What the sites compute from their inputs and what they write from the sums
+// is the physics policy P:
+//
+//   P::Q                      velocity set (19 or 27)
+//   P::C, P::T                compute type, element type of the site offsets
+//   P::Raw<OWN>               per-site inputs (OWN: the site is also a
+//                             destination of this workgroup; halo sites
+//                             only act as sources)
+//   P::Carry                  per-site data a source hands to its own
+//                             destination one plane later
+//   P::fetch<OWN>(a, pb, off, plane_bytes, raw)
+//   P::source<OWN>(a, raw, g[Q], carry)   g in units of 1/D (D = Lat<Q>::D)
+//   P::finish(a, sums, carry, pb, off, plane_bytes)   store one destination
+//
+// gfx950 mapping (own design; the paper's 8x8x8 shared-memory tiles are prior
+// art for another GPU):
+//   * a workgroup owns a 64 x TY column tile of the x-y plane and a chunk of
+//     z-planes, and marches through z;
+//   * wave w (0..TY+1) handles tile row w-1; waves 0 and TY+1 are the y-halo
+//     rows and also compute the two x-halo columns (lanes 0..TY+1);
+//   * per source plane, every thread evaluates its own site once and writes
+//     the values that leave its (x, y) column (16 for D3Q19, 24 for D3Q27) to
+//     LDS; after a barrier each interior thread pulls the 3x3 column
+//     neighbourhood from LDS;
+//   * values travelling along z stay in registers: the ones with c_z=+1 wait
+//     one plane, the ones with c_z=-1 complete the previous plane, so each
+//     input is read from HBM once per update (plus L2-resident halos) and each
+//     output written once, with no population array anywhere;
+//   * block ids are remapped so that each XCD (own L2) gets a contiguous range
+//     of tiles, y-neighbours first: concurrently running tiles share halo rows.
+#pragma once
+
+#ifndef LBF_PREFETCH_DEPTH
+#define LBF_PREFETCH_DEPTH 1
+#endif
+
+#include "internal.hpp"
+#include "lattice.hpp"
+
+namespace lbf {
+
+// Values leaving one site along each direction, in units of 1/D, from the
+// coefficients of the expansion
+//   g_i = k_i [A + sum_a D_a c_ia^2 + sum_{a<b} O_ab c_ia c_ib + sum_a V_a c_ia],
+// k_i = D w_i.
+template <int Q, typename C>
+__device__ __forceinline__ void expand(C A, C Dx, C Dy, C Dz, C Oxy, C Oxz, C Oyz, C Vx, C Vy,
+                                       C Vz, C g[Q]) {
+  using L = Lat<Q>;
+  static_for<Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
+    C v = A;
+    if constexpr (cx != 0) v += Dx;
+    if constexpr (cy != 0) v += Dy;
+    if constexpr (cz != 0) v += Dz;
+    if constexpr (cx * cy == 1) v += Oxy;
+    if constexpr (cx * cy == -1) v -= Oxy;
+    if constexpr (cx * cz == 1) v += Oxz;
+    if constexpr (cx * cz == -1) v -= Oxz;
+    if constexpr (cy * cz == 1) v += Oyz;
+    if constexpr (cy * cz == -1) v -= Oyz;
+    if constexpr (cx == 1) v += Vx;
+    if constexpr (cx == -1) v -= Vx;
+    if constexpr (cy == 1) v += Vy;
+    if constexpr (cy == -1) v -= Vy;
+    if constexpr (cz == 1) v += Vz;
+    if constexpr (cz == -1) v -= Vz;
+    g[i] = (L::k(i) == 1.0) ? v : C(L::k(i)) * v;
+  });
+}
+
+// Running projections of the arriving values (units of 1/D) on H0 (s0),
+// H1 (j) and c c (p), so that values can be folded in as they arrive.
+template <typename C>
+struct Sums {
+  C s0, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz;
+};
+
+template <typename C>
+__device__ __forceinline__ void zero(Sums<C>& S) {
+  S.s0 = S.jx = S.jy = S.jz = S.pxx = S.pyy = S.pzz = S.pxy = S.pxz = S.pyz = C(0);
+}
+
+// add value v arriving along direction i
+template <int Q, int i, typename C>
+__device__ __forceinline__ void accumulate(Sums<C>& S, C v) {
+  using L = Lat<Q>;
+  constexpr int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
+  S.s0 += v;
+  if constexpr (cx == 1) S.jx += v;
+  if constexpr (cx == -1) S.jx -= v;
+  if constexpr (cy == 1) S.jy += v;
+  if constexpr (cy == -1) S.jy -= v;
+  if constexpr (cz == 1) S.jz += v;
+  if constexpr (cz == -1) S.jz -= v;
+  if constexpr (cx != 0) S.pxx += v;
+  if constexpr (cy != 0) S.pyy += v;
+  if constexpr (cz != 0) S.pzz += v;
+  if constexpr (cx * cy == 1) S.pxy += v;
+  if constexpr (cx * cy == -1) S.pxy -= v;
+  if constexpr (cx * cz == 1) S.pxz += v;
+  if constexpr (cx * cz == -1) S.pxz -= v;
+  if constexpr (cy * cz == 1) S.pyz += v;
+  if constexpr (cy * cz == -1) S.pyz -= v;
+}
+
+template <class P, int TY, bool WALLY>
+__global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) {
+  constexpr int Q = P::Q;
+  using L = Lat<Q>;
+  using C = typename P::C;
+  using T = typename P::T;
+  using RawOwn = typename P::template Raw<true>;
+  using RawHalo = typename P::template Raw<false>;
+  using Carry = typename P::Carry;
+  constexpr int NP = L::NP;
+  constexpr int R = TY + 2;  // LDS rows: tile rows plus the two y-halo rows
+  constexpr int W = 66;      // LDS columns: 64 lanes plus the two x-halo columns
+  __shared__ C lds[NP][R][W];
+  __shared__ C colbuf[NP][2][R];  // next plane's x-halo columns (halo waves)
+
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;  // LDS row of this wave's sites
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int64_t plane = static_cast<int64_t>(nx) * ny;
+
+  // Hardware hands consecutive block ids to the 8 XCDs in turn; give each XCD
+  // a contiguous range of logical tiles (y fastest, then x, then z chunk).
+  const int nb = static_cast<int>(gridDim.x), b0 = static_cast<int>(blockIdx.x);
+  const int q8 = nb >> 3, r8 = nb & 7, xcd = b0 & 7;
+  int b = xcd * q8 + (xcd < r8 ? xcd : r8) + (b0 >> 3);
+  const int tyi = b % a.tiles_y;
+  b /= a.tiles_y;
+  const int txi = b % a.tiles_x;
+  const int zci = b / a.tiles_x;
+  const int x0 = txi * 64, y0 = tyi * TY;
+  const int z0 = zci * a.zchunk;
+  const int z1 = min(z0 + a.zchunk, nz);
+
+  // In-plane byte offsets are 32-bit (the host enforces nx*ny*8 < 2^32); the
+  // per-plane base pointers are uniform, so every load and store is a scalar
+  // base plus one vector offset.
+  // own source site (every lane computes a valid, possibly wrapped, site)
+  const int xs = pmod(x0 + lane, nx);
+  const int ys = WALLY ? clampi(y0 + wv - 1, 0, ny - 1) : pmod(y0 + wv - 1, ny);
+  const uint32_t off_s = (static_cast<uint32_t>(ys) * static_cast<uint32_t>(nx) + xs) * sizeof(T);
+  // x-halo site: wave 0 takes the left column, wave R-1 the right one
+  const bool do_halo = (wv == 0 || wv == R - 1) && lane < R;
+  const int hcol = (wv == 0) ? 0 : W - 1;
+  const int xh = pmod(wv == 0 ? x0 - 1 : x0 + 64, nx);
+  const int yh = WALLY ? clampi(y0 - 1 + lane, 0, ny - 1) : pmod(y0 - 1 + lane, ny);
+  const uint32_t off_h = (static_cast<uint32_t>(yh) * static_cast<uint32_t>(nx) + xh) * sizeof(T);
+  // destination
+  const bool interior = (wv >= 1 && wv <= TY);
+  const int xd = x0 + lane, yd = y0 + wv - 1;
+  const bool store_ok = interior && xd < nx && yd < ny;
+  const uint32_t off_d = (static_cast<uint32_t>(yd) * static_cast<uint32_t>(nx) + xd) * sizeof(T);
+  const bool wall_lo = WALLY && interior && yd == 0;
+  const bool wall_hi = WALLY && interior && yd == ny - 1;
+
+  const uint32_t plane_bytes = static_cast<uint32_t>(plane * sizeof(T));
+  // periodic plane index for zs >= -1 (zs is uniform: scalar arithmetic;
+  // planes past the end of a padded chunk are fetched but never used)
+  auto zwrap = [&](int zs) __attribute__((always_inline)) {
+    zs = zs < 0 ? zs + nz : zs;
+    zs = zs >= nz ? zs - nz : zs;
+    return zs >= nz ? zs % nz : zs;
+  };
+  auto fetch_own = [&](const int zs, const uint32_t off, RawOwn& r) __attribute__((always_inline)) {
+    P::template fetch<true>(a, static_cast<int64_t>(zwrap(zs)) * plane, off, plane_bytes, r);
+  };
+  auto fetch_halo = [&](const int zs, const uint32_t off, RawHalo& r) __attribute__((always_inline)) {
+    P::template fetch<false>(a, static_cast<int64_t>(zwrap(zs)) * plane, off, plane_bytes, r);
+  };
+  auto stage = [&](const C g[Q], const int row, const int col) __attribute__((always_inline)) {
+    static_for<NP>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      lds[i][row][col] = g[i];
+    });
+  };
+  // value i arriving at this thread's destination from the LDS plane; on a
+  // wall row the ones that would come from beyond the wall are dropped here
+  // and replaced by the reflections added in body_interior
+  auto pulled = [&](auto I) __attribute__((always_inline)) -> C {
+    constexpr int i = decltype(I)::value;
+    C v = lds[i][wv - L::cy(i)][lane + 1 - L::cx(i)];
+    if constexpr (WALLY && L::cy(i) == 1) v = wall_lo ? C(0) : v;
+    if constexpr (WALLY && L::cy(i) == -1) v = wall_hi ? C(0) : v;
+    return v;
+  };
+
+  // Interior waves, one source plane zs per call.  acc: running sums of
+  // destination plane zs-1 (all but its c_z=-1 values), completed and stored
+  // here; up: the c_z=+1 values that reach plane zs from zs-1; cd: the carry
+  // of the own site of plane zs-1.  rc holds this plane's inputs, rn receives
+  // the next plane's (one plane of latency hiding).
+  constexpr int NU = (Q == 19) ? 5 : 9;  // directions with c_z = +1
+  auto body_interior = [&](const int zs, Sums<C>& acc, C (&up)[NU], Carry& cd, RawOwn& rc,
+                           RawOwn& rn, const int ahead) __attribute__((always_inline)) {
+    // unconditional (the last planes of a chunk fetch unused planes): a
+    // conditional fetch makes the wait-count merge stall on the fresh loads
+    fetch_own(zs + ahead, off_s, rn);
+    C g[Q];
+    Carry cs;
+    P::template source<true>(a, rc, g, cs);
+    stage(g, wv, lane + 1);
+    __syncthreads();
+    // c_z = -1 values complete destination plane zs-1
+    static_for<Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      if constexpr (L::cz(i) == -1) {
+        if constexpr (i < NP)
+          accumulate<Q, i>(acc, pulled(I));
+        else
+          accumulate<Q, i>(acc, g[i]);
+      }
+    });
+    {
+      // Every iteration issues the same stores (uniform memory-op counts keep
+      // the wait counters precise); lanes with nothing to store -- planes
+      // outside the chunk, ragged tails -- use an offset at the end of the
+      // plane, which the buffer range check discards.
+      const bool live = zs - 1 >= z0 && zs - 1 < z1;
+      const int64_t pb = static_cast<int64_t>(live ? zs - 1 : z0) * plane;
+      const uint32_t off = (store_ok && live) ? off_d : plane_bytes;
+      P::finish(a, acc, cd, pb, off, plane_bytes);
+    }
+    // destination plane zs: the c_z=+1 values from zs-1, then c_z = 0
+    zero(acc);
+    {
+      int u = 0;
+      static_for<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (L::cz(i) == 1) accumulate<Q, i>(acc, up[u++]);
+      });
+    }
+    static_for<Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      if constexpr (L::cz(i) == 0) {
+        if constexpr (i < NP)
+          accumulate<Q, i>(acc, pulled(I));
+        else
+          accumulate<Q, i>(acc, g[i]);
+      }
+    });
+    if constexpr (WALLY) {
+      // halfway bounce-back: a value that would come from beyond the wall is
+      // the opposite one leaving x itself at the same time level
+      if (wall_lo)
+        static_for<Q>([&](auto I) {
+          constexpr int i = decltype(I)::value;
+          if constexpr (L::cy(i) == 1) accumulate<Q, i>(acc, g[L::opp(i)]);
+        });
+      if (wall_hi)
+        static_for<Q>([&](auto I) {
+          constexpr int i = decltype(I)::value;
+          if constexpr (L::cy(i) == -1) accumulate<Q, i>(acc, g[L::opp(i)]);
+        });
+    }
+    cd = cs;
+    // c_z = +1 values for destination plane zs+1
+    {
+      int u = 0;
+      static_for<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (L::cz(i) == 1) {
+          if constexpr (i < NP)
+            up[u++] = pulled(I);
+          else
+            up[u++] = g[i];
+        }
+      });
+    }
+    __syncthreads();
+  };
+
+  // Halo waves: their own y-halo row, plus one x-halo column site per lane
+  // (lanes 0..R-1).  To balance the two phases of a plane against the
+  // interior waves (evaluate, then pull + project), the column site of plane
+  // zs+1 is evaluated during phase 2 of plane zs into colbuf, and copied into
+  // the plane's column slots during phase 1 of zs+1 (same lane writes and
+  // reads colbuf, so it needs no barrier of its own).
+  const int hwave = (wv == 0) ? 0 : 1;
+  // lanes without an x-halo site fetch at the plane end: zeros, no fault
+  const uint32_t off_hf = do_halo ? off_h : plane_bytes;
+  auto col_to_buf = [&](const RawHalo& r) __attribute__((always_inline)) {
+    C g[Q];
+    Carry cs;
+    P::template source<false>(a, r, g, cs);
+    if (do_halo)
+      static_for<NP>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        colbuf[i][hwave][lane] = g[i];
+      });
+  };
+  // rc: this plane's row site, rn: receives plane zs+ahead; hc: the column
+  // site of plane zs+1, refilled after use with plane zs+1+U
+  auto body_halo = [&](const int zs, RawHalo& rc, RawHalo& rn, RawHalo& hc,
+                       const int ahead) __attribute__((always_inline)) {
+    fetch_halo(zs + ahead, off_s, rn);
+    if (do_halo)
+      static_for<NP>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        lds[i][lane][hcol] = colbuf[i][hwave][lane];
+      });
+    {
+      C g[Q];
+      Carry cs;
+      P::template source<false>(a, rc, g, cs);
+      stage(g, wv, lane + 1);
+    }
+    __syncthreads();
+    col_to_buf(hc);
+    fetch_halo(zs + 1 + (ahead + 1), off_hf, hc);
+    __syncthreads();
+  };
+
+  // The role is uniform per wave; the two roles run separate loops so that
+  // their loop-carried registers never coexist.  Both run the same padded
+  // number of source planes (z0-1 .. z1, rounded up to a multiple of the
+  // unroll U) with exactly two barriers each; padded planes compute values
+  // that are never stored.  Every path through a loop trip issues the same
+  // memory operations, which keeps the compiler's wait counts exact.
+  constexpr int PF = LBF_PREFETCH_DEPTH;  // planes of inputs in flight
+  constexpr int U = PF + 1;               // rotating raw buffers = unroll
+  const int trips = ((z1 - z0 + 2) + U - 1) / U;
+  const bool interior_wave = __builtin_amdgcn_readfirstlane(static_cast<int>(interior)) != 0;
+  if (interior_wave) {
+    Sums<C> acc;
+    zero(acc);
+    C up[NU];
+    Carry cd;
+    P::clear(cd);
+#pragma unroll
+    for (int u = 0; u < NU; ++u) up[u] = C(0);
+    RawOwn rr[U];
+    static_for<PF>([&](auto J) { fetch_own(z0 - 1 + J, off_s, rr[J]); });
+#pragma unroll 1
+    for (int t = 0; t < trips; ++t) {
+      const int zb = z0 - 1 + t * U;
+      static_for<U>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        body_interior(zb + k, acc, up, cd, rr[k], rr[(k + PF) % U], PF);
+      });
+    }
+  } else {
+    RawHalo rr[U], hh[U];
+    {
+      RawHalo first;
+      fetch_halo(z0 - 1, off_hf, first);
+      col_to_buf(first);  // columns of the first source plane
+    }
+    static_for<U>([&](auto J) { fetch_halo(z0 + J, off_hf, hh[J]); });
+    static_for<PF>([&](auto J) { fetch_halo(z0 - 1 + J, off_s, rr[J]); });
+#pragma unroll 1
+    for (int t = 0; t < trips; ++t) {
+      const int zb = z0 - 1 + t * U;
+      static_for<U>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        body_halo(zb + k, rr[k], rr[(k + PF) % U], hh[k], PF);
+      });
+    }
+  }
+}
+
+// LDS bytes of one workgroup: NP staged values x (TY+2) rows x 66 columns
+template <int Q, typename C, int TY>
+constexpr size_t march_lds_bytes() {
+  return sizeof(C) * Lat<Q>::NP * (TY + 2) * 66;
+}
+constexpr size_t kLdsLimit = 160 * 1024;
+
+template <class P, int TY, bool WALLY>
+hipError_t launch_march(const StepArgs& a, hipStream_t stream) {
+  if constexpr (march_lds_bytes<P::Q, typename P::C, TY>() > kLdsLimit) {
+    return hipErrorInvalidConfiguration;
+  } else {
+    const int nb = a.tiles_x * a.tiles_y * a.zchunks;
+    hipLaunchKernelGGL((march_kernel<P, TY, WALLY>), dim3(nb), dim3(64 * (TY + 2)), 0, stream, a);
+    return hipGetLastError();
+  }
+}
+
+}  // namespace lbf

@@ -37,6 +37,30 @@ def oracle_run(shape, tau, m0, steps, lattice=19, bc=(0, 0, 0), force=None):
     return o.moments()
 
 
+_CACHE = {}
+
+
+def solenoidal_oracle_1000(Q, n=64, tau=0.6):
+    """Oracle moments after 1000 steps of the n^3 solenoidal workload (cached:
+    several storage types compare against the same reference)."""
+    key = (Q, n, tau)
+    if key not in _CACHE:
+        m0 = __import__("paper_2609_09160_amd.inputs", fromlist=["x"]).solenoidal_field((n, n, n))
+        _CACHE[key] = (m0, oracle_run((n, n, n), tau, m0, 1000, lattice=Q))
+    return _CACHE[key]
+
+
+def oracle_site_update(crop, Q, tau):
+    """One oracle step at the centre of a 3x3x3 neighbourhood [10, 3, 3, 3]
+    (z, y, x): the pull at the centre reads only its 26 neighbours, so a
+    periodic 3^3 box gives the exact update of that site."""
+    import oracle
+    o = oracle.PopulationOracle(Q, (3, 3, 3), tau)
+    o.set_moments(np.ascontiguousarray(crop))
+    o.step(1)
+    return o.moments()[:, 1, 1, 1]
+
+
 def state_rel_err(got, want):
     """max|got - want| over all moments / max|want| over all moments, and the
     same for the velocity group alone; rounding scales with the state's
