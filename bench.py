@@ -128,6 +128,64 @@ def stream_ceiling(n=512 ** 3, nplanes=10, reps=5):
     return nbytes / (ms * 1e-3) / 1e9, ms, nbytes
 
 
+ADJ_BYTES_PER_LUP = 140   # adjoint step: read lambda' 40, F 12, u(t+1) 12, u(t) 12, gF 12;
+                          # write lambda 40, gF 12 (FP32)
+FWD_F_BYTES_PER_LUP = 92  # forward step with a per-site force field: 40 + 12 read, 40 written
+
+
+def run_adjoint(n=192, steps=500, every=50, reps=2):
+    """Adjoint workload: D3Q19 FP32 n^3 periodic, tau = 0.8, from rest, per-site
+    force std 1e-6 (seed 160), J = 1/2 sum |u(T)|^2, checkpoints every 50.
+    Adjoint MLUPS = sites * steps / backward time (segment recomputation
+    included)."""
+    import torch
+    from paper_2609_09160_amd import Solver, inputs
+    shape = (n, n, n)
+    s = Solver(shape, 0.8, storage="f32")
+    F = torch.as_tensor(inputs.random_force(shape, seed=160, std=1e-6), device="cuda",
+                        dtype=torch.float32)
+    s.set_force_field(F)
+    m0 = torch.zeros((10, n, n, n), dtype=torch.float32, device="cuda")
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    best_f = best_b = None
+    for _ in range(reps):
+        s.set_moments(m0)
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record(s.stream)
+        ckpt = s.forward_checkpointed(steps, every)
+        e1.record(s.stream)
+        mT = s.moments(dtype=torch.float32)
+        lam = torch.zeros_like(mT)
+        lam[1:4] = mT[1:4]
+        torch.cuda.synchronize()
+        b0, b1 = ev(), ev()
+        b0.record(s.stream)
+        gF, _ = s.adjoint(steps, every, ckpt, lam, want_m0=False)
+        b1.record(s.stream)
+        torch.cuda.synchronize()
+        tf, tb = e0.elapsed_time(e1), b0.elapsed_time(b1)
+        best_f = tf if best_f is None else min(best_f, tf)
+        best_b = tb if best_b is None else min(best_b, tb)
+        finite = bool(torch.isfinite(gF).all())
+        del ckpt, gF
+    s.close()
+    torch.cuda.empty_cache()
+    sites = n ** 3
+    adj_step_ms = (best_b - best_f) / steps  # backward minus one recomputation pass
+    adj_gbs = ADJ_BYTES_PER_LUP * sites / (adj_step_ms * 1e-3) / 1e9
+    return {"mlups": round(sites * steps / (best_b * 1e-3) / 1e6, 1),
+            "workload": f"D3Q19 FP32 {n}^3 periodic, tau=0.8, from rest, per-site force "
+                        f"std 1e-6 (seed 160), J=1/2 sum|u({steps})|^2, checkpoint every {every}",
+            "ms_backward": round(best_b, 3), "ms_forward_checkpointed": round(best_f, 3),
+            "adjoint_step_ms": round(adj_step_ms, 5),
+            "adjoint_step_bytes_per_lup": ADJ_BYTES_PER_LUP,
+            "adjoint_step_GBs": round(adj_gbs, 1),
+            "adjoint_step_hbm_frac": round(adj_gbs / HBM_PEAK_GBS, 4),
+            "backward_bytes_per_lup": ADJ_BYTES_PER_LUP + FWD_F_BYTES_PER_LUP,
+            "finite": finite}
+
+
 def cpu_baseline(lattice, budget_s=20.0):
     """The FP64 CPU oracle on the host cores, bounded sample of the workload."""
     import numpy as np
@@ -164,6 +222,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the short runs of D3Q27, FP64 and 16-bit storage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--tile-rows", type=int, default=0, help="launch override (0 = default)")
     ap.add_argument("--z-chunk", type=int, default=0, help="launch override (0 = default)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -239,6 +298,8 @@ def main():
                                      "algorithmic_GBs": round(r["algorithmic_GBs"], 1),
                                      "hbm_frac": round(r["hbm_frac"], 4)}
         out["variants"] = var
+    if not args.no_adjoint:
+        out["adjoint"] = run_adjoint()
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         out["cpu_baseline"] = cpu_baseline(args.lattice)
     print(json.dumps(out), flush=True)

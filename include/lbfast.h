@@ -149,6 +149,36 @@ int lbfast_get_scales(lbfast_t h, float out[10]);
  * reproducible from run to run. */
 int lbfast_set_launch(lbfast_t h, int tile_rows, int z_chunk);
 
+/* Discrete adjoint (the paper does not treat differentiation; this is the
+ * exact reverse mode of the discrete step of Eqs. (7)-(9) as implemented by
+ * lbfast_step, for F64 and F32 storage; LBF_E_UNSUPPORTED for 16-bit).
+ * The objective J is any function of the final state m(T); the caller gives
+ * lambda_T = dJ/dm(T) and receives dJ/dF (gradient with respect to the
+ * per-site force field, static in time) and optionally dJ/dm(0).  Gradients
+ * with respect to the second-order planes are taken per stored component
+ * (an off-diagonal plane stands for both symmetric entries).
+ *
+ * Checkpointing: lbfast_forward_checkpointed advances the state by nsteps,
+ * saving the state at t = 0, k, 2k, ... (k = every) into ckpt_dev, which
+ * holds ceil(nsteps/k) buffers of lbfast_buffer_bytes(p) bytes (device,
+ * caller-owned, 256-byte aligned).  lbfast_adjoint then walks the segments
+ * backwards: each is recomputed from its checkpoint into work_dev (k + 2
+ * buffers of lbfast_buffer_bytes(p): the k recomputed states and two
+ * adjoint buffers; see lbfast_adjoint_work_bytes) and swept with one adjoint
+ * step per time step.  The force (field or uniform), tau, lattice and
+ * boundaries in use must be those of the forward run.
+ *
+ * Arrays (device, compute type: double for F64, float for F32 storage):
+ *   lambda_T_dev  10 x N, read only;
+ *   gF_dev        3 x N, overwritten with dJ/dF;
+ *   lambda0_dev   10 x N, overwritten with dJ/dm(0), or NULL.
+ * Both calls are asynchronous on the handle's stream; the handle's own
+ * state is left at m(T).  nsteps = 0 gives gF = 0 and lambda0 = lambda_T. */
+int lbfast_forward_checkpointed(lbfast_t h, int64_t nsteps, int64_t every, void* ckpt_dev);
+size_t lbfast_adjoint_work_bytes(lbfast_t h, int64_t every);
+int lbfast_adjoint(lbfast_t h, int64_t nsteps, int64_t every, const void* ckpt_dev,
+                   const void* lambda_T_dev, void* gF_dev, void* lambda0_dev, void* work_dev);
+
 /* Measurement utility, not part of the method: copy `nplanes` planes of `n`
  * floats from src to dst (device pointers, n * 4 < 2^32) on `stream`, using
  * the same memory instruction forms as the step (dword buffer loads,

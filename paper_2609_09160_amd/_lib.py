@@ -69,6 +69,9 @@ def load():
         "lbfast_set_launch": ([vp, i32, i32], i32),
         "lbfast_last_error": ([], ctypes.c_char_p),
         "lbfast_stream_probe": ([vp, vp, i64, i32, vp], i32),
+        "lbfast_forward_checkpointed": ([vp, i64, i64, vp], i32),
+        "lbfast_adjoint_work_bytes": ([vp, i64], ctypes.c_size_t),
+        "lbfast_adjoint": ([vp, i64, i64, vp, vp, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -24,9 +24,28 @@ hipError_t launch_step(int Q, int storage, int tile_rows, bool walls_y, const St
   }
 }
 
+hipError_t launch_adjoint_f64(int, int, bool, bool, const StepArgs&, hipStream_t);
+hipError_t launch_adjoint_f32(int, int, bool, bool, const StepArgs&, hipStream_t);
+
+hipError_t launch_adjoint(int Q, int storage, int tile_rows, bool walls_y, const StepArgs& a,
+                          hipStream_t stream) {
+  const bool ff = a.Ffield != nullptr;
+  switch (storage) {
+    case kF64: return launch_adjoint_f64(Q, tile_rows, walls_y, ff, a, stream);
+    case kF32: return launch_adjoint_f32(Q, tile_rows, walls_y, ff, a, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 namespace {
 
 constexpr int kThreads = 256;
+
+__global__ void zero_kernel(uint32_t* __restrict__ p, int64_t n) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads)
+    p[i] = 0u;
+}
 
 // 10 scales passed by value
 struct Scales {
@@ -259,6 +278,15 @@ hipError_t reduce_st(const void* buf, int64_t N, const float* scale, double* par
 }
 
 }  // namespace
+
+hipError_t launch_zero(void* p, int64_t nbytes, hipStream_t stream) {
+  if (nbytes % 4 != 0) return hipErrorInvalidValue;
+  const int64_t n = nbytes / 4;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_kernel, dim3(grid_for(n)), dim3(kThreads), 0, stream,
+                     static_cast<uint32_t*>(p), n);
+  return hipGetLastError();
+}
 
 hipError_t launch_stream_probe(const void* src, void* dst, int64_t n, int nplanes,
                                hipStream_t s) {

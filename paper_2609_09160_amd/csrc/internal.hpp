@@ -19,6 +19,10 @@ struct StepArgs {
   double F[3];         // uniform force (used when Ffield == nullptr)
   float scale[10];     // 16-bit storage: value = scale * q
   float inv_scale[10];
+  // adjoint step only (src/dst then hold the adjoint variables at t+1 / t)
+  const void* state_old;  // moments at t (10 planes; the velocity planes are read)
+  const void* state_new;  // moments at t+1
+  void* gF;               // 3 planes, dJ/dF accumulated in place
 };
 
 // rows per tile supported by the step kernel
@@ -28,6 +32,14 @@ constexpr int kTileRowsSupported[] = {4, 6, 8, 14};
 // combination.  nblocks = tiles_x * tiles_y * zchunks.
 hipError_t launch_step(int Q, int storage, int tile_rows, bool walls_y, const StepArgs& a,
                        hipStream_t stream);
+
+// One step of the discrete adjoint (FP64 or FP32 storage only).
+hipError_t launch_adjoint(int Q, int storage, int tile_rows, bool walls_y, const StepArgs& a,
+                          hipStream_t stream);
+
+// zero nbytes bytes (a multiple of 4) with a kernel, so that graph capture
+// records no memset node
+hipError_t launch_zero(void* p, int64_t nbytes, hipStream_t stream);
 
 // copy nplanes planes of n floats (n * 4 < 2^32) with the step's memory
 // instruction forms

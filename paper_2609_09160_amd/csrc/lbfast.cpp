@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -171,6 +172,39 @@ bool is_device_ptr(const void* p) {
     return false;
   }
   return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+}
+
+// launch geometry, relaxation, force and scales of the handle's step
+int step_args(const lbfast_ctx* h, lbf::StepArgs* a) {
+  *a = lbf::StepArgs{};
+  a->nx = static_cast<int>(h->p.nx);
+  a->ny = static_cast<int>(h->p.ny);
+  a->nz = static_cast<int>(h->p.nz);
+  a->N = h->N;
+  if (int rc = resolve_zchunk(h, &a->tiles_x, &a->tiles_y, &a->zchunks, &a->zchunk)) return rc;
+  a->omega = 1.0 / h->p.tau;
+  for (int k = 0; k < 3; ++k) a->F[k] = h->Ffield ? 0.0 : h->p.force[k];
+  for (int k = 0; k < 10; ++k) {
+    a->scale[k] = h->scale[k];
+    a->inv_scale[k] = h->inv_scale[k];
+  }
+  a->Ffield = h->Ffield;
+  return LBF_OK;
+}
+
+int launch_forward(const lbfast_ctx* h, const lbf::StepArgs& a) {
+  hipError_t e = lbf::launch_step(h->p.lattice, h->p.storage, h->tile_rows,
+                                  h->p.bc[1] == LBF_WALLS, a, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "step launch");
+  return LBF_OK;
+}
+
+int check_adjoint_args(const lbfast_ctx* h, int64_t nsteps, int64_t every) {
+  if (h->p.storage != LBF_F64 && h->p.storage != LBF_F32)
+    return fail(LBF_E_UNSUPPORTED, "the adjoint supports F64 and F32 storage only");
+  if (nsteps < 0) return fail(LBF_E_ARG, "nsteps must be >= 0");
+  if (every < 1) return fail(LBF_E_ARG, "every must be >= 1");
+  return LBF_OK;
 }
 
 }  // namespace
@@ -446,25 +480,110 @@ int lbfast_step(lbfast_t h, int64_t n) {
   if (!h->scales_fixed) return fail(LBF_E_STATE, "16-bit scales not set: call set_moments first");
   DeviceGuard g(h->device);
   lbf::StepArgs a;
-  a.nx = static_cast<int>(h->p.nx);
-  a.ny = static_cast<int>(h->p.ny);
-  a.nz = static_cast<int>(h->p.nz);
-  a.N = h->N;
-  if (int rc = resolve_zchunk(h, &a.tiles_x, &a.tiles_y, &a.zchunks, &a.zchunk)) return rc;
-  a.omega = 1.0 / h->p.tau;
-  for (int k = 0; k < 3; ++k) a.F[k] = h->Ffield ? 0.0 : h->p.force[k];
-  for (int k = 0; k < 10; ++k) {
-    a.scale[k] = h->scale[k];
-    a.inv_scale[k] = h->inv_scale[k];
-  }
-  a.Ffield = h->Ffield;
-  const bool walls_y = h->p.bc[1] == LBF_WALLS;
+  if (int rc = step_args(h, &a)) return rc;
   for (int64_t s = 0; s < n; ++s) {
     a.src = h->buf[h->cur];
     a.dst = h->buf[h->cur ^ 1];
-    hipError_t e = lbf::launch_step(h->p.lattice, h->p.storage, h->tile_rows, walls_y, a, h->stream);
-    if (e != hipSuccess) return hip_fail(e, "step launch");
+    if (int rc = launch_forward(h, a)) return rc;
     h->cur ^= 1;
+  }
+  return LBF_OK;
+}
+
+int lbfast_forward_checkpointed(lbfast_t h, int64_t nsteps, int64_t every, void* ckpt_dev) {
+  g_err.clear();
+  if (int rc = check_handle(h)) return rc;
+  if (int rc = check_adjoint_args(h, nsteps, every)) return rc;
+  if (nsteps > 0 && !ckpt_dev) return fail(LBF_E_ARG, "ckpt_dev is NULL");
+  if (reinterpret_cast<uintptr_t>(ckpt_dev) & 255)
+    return fail(LBF_E_ARG, "ckpt_dev must be 256-byte aligned");
+  DeviceGuard g(h->device);
+  const size_t bytes = lbfast_buffer_bytes(&h->p);
+  lbf::StepArgs a;
+  if (int rc = step_args(h, &a)) return rc;
+  for (int64_t t = 0; t < nsteps; ++t) {
+    if (t % every == 0) {
+      hipError_t e = hipMemcpyAsync(static_cast<char*>(ckpt_dev) + (t / every) * bytes,
+                                    h->buf[h->cur], bytes, hipMemcpyDeviceToDevice, h->stream);
+      if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
+    }
+    a.src = h->buf[h->cur];
+    a.dst = h->buf[h->cur ^ 1];
+    if (int rc = launch_forward(h, a)) return rc;
+    h->cur ^= 1;
+  }
+  return LBF_OK;
+}
+
+size_t lbfast_adjoint_work_bytes(lbfast_t h, int64_t every) {
+  if (!h || every < 1) return 0;
+  return static_cast<size_t>(every + 2) * lbfast_buffer_bytes(&h->p);
+}
+
+int lbfast_adjoint(lbfast_t h, int64_t nsteps, int64_t every, const void* ckpt_dev,
+                   const void* lambda_T_dev, void* gF_dev, void* lambda0_dev, void* work_dev) {
+  g_err.clear();
+  if (int rc = check_handle(h)) return rc;
+  if (int rc = check_adjoint_args(h, nsteps, every)) return rc;
+  if (!lambda_T_dev || !gF_dev) return fail(LBF_E_ARG, "lambda_T_dev and gF_dev are required");
+  if (nsteps > 0 && (!ckpt_dev || !work_dev))
+    return fail(LBF_E_ARG, "ckpt_dev and work_dev are required for nsteps > 0");
+  const size_t ce = (h->p.storage == LBF_F64) ? 8 : 4;
+  for (const void* p : {ckpt_dev, static_cast<const void*>(work_dev)})
+    if (reinterpret_cast<uintptr_t>(p) & 255)
+      return fail(LBF_E_ARG, "ckpt_dev and work_dev must be 256-byte aligned");
+  for (const void* p : {lambda_T_dev, static_cast<const void*>(gF_dev),
+                        static_cast<const void*>(lambda0_dev)})
+    if (reinterpret_cast<uintptr_t>(p) & (ce - 1))
+      return fail(LBF_E_ARG, "adjoint arrays must be aligned to the compute type");
+  DeviceGuard g(h->device);
+  const size_t bytes = lbfast_buffer_bytes(&h->p);
+  const int64_t N = h->N;
+  hipError_t e = lbf::launch_zero(gF_dev, 3 * N * static_cast<int64_t>(ce), h->stream);
+  if (e != hipSuccess) return hip_fail(e, "zero dJ/dF");
+  if (nsteps == 0) {
+    if (lambda0_dev) {
+      e = hipMemcpyAsync(lambda0_dev, lambda_T_dev, bytes, hipMemcpyDeviceToDevice, h->stream);
+      if (e != hipSuccess) return hip_fail(e, "adjoint copy");
+    }
+    return LBF_OK;
+  }
+  char* work = static_cast<char*>(work_dev);
+  // work: recomputed states 1..every of a segment, then two adjoint buffers
+  void* lam[2] = {work + every * bytes, work + (every + 1) * bytes};
+  e = hipMemcpyAsync(lam[0], lambda_T_dev, bytes, hipMemcpyDeviceToDevice, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "adjoint copy");
+  int cur = 0;
+  lbf::StepArgs fa, aa;
+  if (int rc = step_args(h, &fa)) return rc;
+  aa = fa;
+  aa.gF = gF_dev;
+  const int64_t nseg = (nsteps + every - 1) / every;
+  const bool walls_y = h->p.bc[1] == LBF_WALLS;
+  for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+    const int64_t len = std::min(every, nsteps - seg * every);
+    auto state = [&](int64_t j) -> void* {  // state at t = seg*every + j
+      return j == 0 ? static_cast<void*>(static_cast<char*>(const_cast<void*>(ckpt_dev)) + seg * bytes)
+                    : static_cast<void*>(work + (j - 1) * bytes);
+    };
+    for (int64_t j = 0; j < len; ++j) {  // recompute the segment
+      fa.src = state(j);
+      fa.dst = state(j + 1);
+      if (int rc = launch_forward(h, fa)) return rc;
+    }
+    for (int64_t j = len - 1; j >= 0; --j) {  // sweep it backwards
+      aa.src = lam[cur];
+      aa.dst = lam[cur ^ 1];
+      aa.state_old = state(j);
+      aa.state_new = state(j + 1);
+      e = lbf::launch_adjoint(h->p.lattice, h->p.storage, h->tile_rows, walls_y, aa, h->stream);
+      if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+      cur ^= 1;
+    }
+  }
+  if (lambda0_dev) {
+    e = hipMemcpyAsync(lambda0_dev, lam[cur], bytes, hipMemcpyDeviceToDevice, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint copy");
   }
   return LBF_OK;
 }

@@ -120,6 +120,47 @@ class Solver:
         check(rc)
         return np.array(out[:])
 
+    # -- discrete adjoint ----------------------------------------------------------
+    def buffer_bytes(self):
+        return self._bufs[0].numel()
+
+    def forward_checkpointed(self, nsteps, every):
+        """Advance nsteps, saving the state every `every` steps; returns the
+        checkpoint tensor (ceil(nsteps/every) state buffers) for adjoint()."""
+        torch = self._torch
+        nseg = (int(nsteps) + int(every) - 1) // int(every) if nsteps > 0 and every > 0 else 0
+        ckpt = torch.empty(max(nseg, 1) * self.buffer_bytes(), dtype=torch.uint8,
+                           device=self.device)
+        check(self.lib.lbfast_forward_checkpointed(self.h, int(nsteps), int(every),
+                                                   ctypes.c_void_p(ckpt.data_ptr())))
+        return ckpt
+
+    def adjoint(self, nsteps, every, ckpt, lam_T, want_m0=True):
+        """Reverse sweep over the nsteps run by forward_checkpointed: for
+        lam_T = dJ/dm(T) (10 x N), returns (dJ/dF [3, nz, ny, nx],
+        dJ/dm(0) [10, nz, ny, nx] or None), in the compute dtype."""
+        torch = self._torch
+        nx, ny, nz = self.shape
+        lam_T = lam_T.to(device=self.device, dtype=self.compute_dtype).contiguous()
+        if lam_T.numel() != N_MOMENTS * self.N:
+            raise ValueError("lam_T must have 10 x N values")
+        gF = torch.empty((3, nz, ny, nx), dtype=self.compute_dtype, device=self.device)
+        lam0 = torch.empty((N_MOMENTS, nz, ny, nx), dtype=self.compute_dtype,
+                           device=self.device) if want_m0 else None
+        wb = self.lib.lbfast_adjoint_work_bytes(self.h, int(every))
+        if wb == 0:
+            check(_lib.LBF_E_ARG)
+        work = torch.empty(wb, dtype=torch.uint8, device=self.device)
+        check(self.lib.lbfast_adjoint(self.h, int(nsteps), int(every),
+                                      ctypes.c_void_p(ckpt.data_ptr()),
+                                      ctypes.c_void_p(lam_T.data_ptr()),
+                                      ctypes.c_void_p(gF.data_ptr()),
+                                      ctypes.c_void_p(lam0.data_ptr() if want_m0 else None),
+                                      ctypes.c_void_p(work.data_ptr())))
+        self.sync()
+        del work
+        return gF, lam0
+
     def state_ptr(self):
         p = ctypes.c_void_p()
         check(self.lib.lbfast_state_ptr(self.h, ctypes.byref(p)))
