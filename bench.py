@@ -24,7 +24,8 @@ METRIC = "MLUPS + % HBM roofline, D3Q19 512^3 FP32 vs 16-bit moments; adjoint ML
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, AMD published peak
 BYTES_PER_VALUE = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
 CSRC = os.path.join(ROOT, "paper_2609_09160_amd", "csrc")
-KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("step_kernel.hpp", "lattice.hpp", "step_f32.hip")]
+KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("march.hpp", "step_kernel.hpp", "lattice.hpp",
+                                                "internal.hpp", "step_f32.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_d3q19_f32_512.txt")
 
 
