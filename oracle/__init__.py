@@ -13,6 +13,10 @@ Contents
   * `moment_form` -- independent NumPy evaluation of the moment-space update
     Eq. (7) + Eq. (8) with generic Hermite tensors (tiny grids).
   * `lattice_tables(Q)` -- the velocity set the C oracle uses.
+  * `two_phase` -- the two-component variant (phase field by the conservative
+    Allen-Cahn equation, Eq. (2), capillary force, flow step with a force
+    that changes every step) and the Laplace measurement.
+  * `adjoint` -- FP64 discrete adjoint of the population oracle.
 """
 import ctypes
 import os
@@ -42,8 +46,14 @@ def _load():
     lib.oracle_stream.argtypes = [ctypes.c_int, i64, i64, i64, ip, dp, dp]
     lib.oracle_run.argtypes = [ctypes.c_int, i64, i64, i64, ip, ctypes.c_double, dp, dp,
                                dp, i64]
+    lib.oracle_grad.argtypes = [i64, i64, i64, dp, dp]
+    lib.oracle_lap.argtypes = [i64, i64, i64, dp, dp]
+    d = ctypes.c_double
+    lib.oracle_phase_step.argtypes = [i64, i64, i64, dp, dp, d, d, d, dp]
+    lib.oracle_capillary_force.argtypes = [i64, i64, i64, dp, d, d, dp, dp]
     for f in ("oracle_init", "oracle_moments", "oracle_collide", "oracle_stream",
-              "oracle_run"):
+              "oracle_run", "oracle_grad", "oracle_lap", "oracle_phase_step",
+              "oracle_capillary_force"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib

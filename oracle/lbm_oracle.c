@@ -293,3 +293,141 @@ int oracle_run(int Q, int64_t nx, int64_t ny, int64_t nz, const int* bc, double 
   }
   return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Two-component variant (section 2): phase field phi transported by the
+ * conservative Allen-Cahn equation, Eq. (2), advanced by forward-time,
+ * centred-space differences; capillary force F^s = mu grad(phi) with the
+ * chemical potential mu = 4 beta phi (phi - 1)(phi - 1/2) - kappa lap(phi),
+ * beta = 12 sigma / W, kappa = 3 sigma W / 2.  Spatial derivatives use the
+ * D3Q27-weighted stencils of section 2:
+ *   grad_a Psi(x) = (1/cs^2) sum_i w_i Psi(x + c_i) c_ia,
+ *   lap Psi(x)    = (2/cs^2) sum_{i != 0} w_i [Psi(x + c_i) - Psi(x)]
+ * (the printed Laplacian stencil is garbled; this is the second-order
+ * Taylor-consistent form, zero on constants).  Periodic grid only.
+ * ------------------------------------------------------------------------ */
+
+static int64_t wrap1(int64_t v, int64_t n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+/* index of the periodic neighbour x + c (c in {-1, 0, 1}^3) */
+static int64_t site_shift(int64_t x, int64_t y, int64_t z, const int c[3], int64_t nx,
+                          int64_t ny, int64_t nz) {
+  return wrap1(x + c[0], nx) + nx * (wrap1(y + c[1], ny) + ny * wrap1(z + c[2], nz));
+}
+
+/* out[a*N + s] = grad_a of the scalar field v at every site */
+int oracle_grad(int64_t nx, int64_t ny, int64_t nz, const double* v, double* out) {
+  lattice_t L;
+  if (make_lattice(27, &L)) return -1;
+  const int64_t N = nx * ny * nz;
+#pragma omp parallel for schedule(static)
+  for (int64_t z = 0; z < nz; ++z)
+    for (int64_t y = 0; y < ny; ++y)
+      for (int64_t x = 0; x < nx; ++x) {
+        const int64_t s = x + nx * (y + ny * z);
+        double g[3] = {0, 0, 0};
+        for (int i = 0; i < 27; ++i) {
+          const double vi = v[site_shift(x, y, z, L.c[i], nx, ny, nz)];
+          for (int a = 0; a < 3; ++a) g[a] += L.w[i] * vi * L.c[i][a];
+        }
+        for (int a = 0; a < 3; ++a) out[a * N + s] = g[a] / CS2;
+      }
+  return 0;
+}
+
+/* out[s] = lap of v at every site */
+int oracle_lap(int64_t nx, int64_t ny, int64_t nz, const double* v, double* out) {
+  lattice_t L;
+  if (make_lattice(27, &L)) return -1;
+#pragma omp parallel for schedule(static)
+  for (int64_t z = 0; z < nz; ++z)
+    for (int64_t y = 0; y < ny; ++y)
+      for (int64_t x = 0; x < nx; ++x) {
+        const int64_t s = x + nx * (y + ny * z);
+        double acc = 0.0;
+        for (int i = 0; i < 27; ++i) {
+          if (L.c[i][0] == 0 && L.c[i][1] == 0 && L.c[i][2] == 0) continue;
+          acc += L.w[i] * (v[site_shift(x, y, z, L.c[i], nx, ny, nz)] - v[s]);
+        }
+        out[s] = 2.0 * acc / CS2;
+      }
+  return 0;
+}
+
+/* out[s] = div of the vector field V (3 planes) at every site */
+static int oracle_div(int64_t nx, int64_t ny, int64_t nz, const double* V, double* out) {
+  lattice_t L;
+  if (make_lattice(27, &L)) return -1;
+  const int64_t N = nx * ny * nz;
+#pragma omp parallel for schedule(static)
+  for (int64_t z = 0; z < nz; ++z)
+    for (int64_t y = 0; y < ny; ++y)
+      for (int64_t x = 0; x < nx; ++x) {
+        const int64_t s = x + nx * (y + ny * z);
+        double acc = 0.0;
+        for (int i = 0; i < 27; ++i) {
+          const int64_t si = site_shift(x, y, z, L.c[i], nx, ny, nz);
+          for (int a = 0; a < 3; ++a) acc += L.w[i] * L.c[i][a] * V[a * N + si];
+        }
+        out[s] = acc / CS2;
+      }
+  return 0;
+}
+
+/* One FTCS step of Eq. (2) in conservative form (unit time step):
+ *   phi' = phi - div(phi u) + D lap(phi) - lambda div(phi (1 - phi) n),
+ * lambda = 4 D / W, n = grad(phi) / (|grad(phi)| + eps).  u: 3 planes. */
+int oracle_phase_step(int64_t nx, int64_t ny, int64_t nz, const double* phi, const double* u,
+                      double D, double W, double eps, double* phi_new) {
+  const int64_t N = nx * ny * nz;
+  double* g = malloc(sizeof(double) * 3 * N);
+  double* V = malloc(sizeof(double) * 3 * N);
+  double* J = malloc(sizeof(double) * 3 * N);
+  double* t1 = malloc(sizeof(double) * N);
+  double* t2 = malloc(sizeof(double) * N);
+  double* t3 = malloc(sizeof(double) * N);
+  int rc = (g && V && J && t1 && t2 && t3) ? 0 : -1;
+  const double lambda = 4.0 * D / W;
+  if (!rc) rc = oracle_grad(nx, ny, nz, phi, g);
+  if (!rc) {
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < N; ++s) {
+      const double gx = g[s], gy = g[N + s], gz = g[2 * N + s];
+      const double mag = sqrt(gx * gx + gy * gy + gz * gz);
+      const double c = phi[s] * (1.0 - phi[s]) / (mag + eps);
+      for (int a = 0; a < 3; ++a) {
+        V[a * N + s] = phi[s] * u[a * N + s];
+        J[a * N + s] = c * g[a * N + s];
+      }
+    }
+    rc = oracle_div(nx, ny, nz, V, t1);
+  }
+  if (!rc) rc = oracle_lap(nx, ny, nz, phi, t2);
+  if (!rc) rc = oracle_div(nx, ny, nz, J, t3);
+  if (!rc)
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < N; ++s) phi_new[s] = phi[s] - t1[s] + D * t2[s] - lambda * t3[s];
+  free(g); free(V); free(J); free(t1); free(t2); free(t3);
+  return rc;
+}
+
+/* Capillary force F^s = mu grad(phi), plus a body force Fb (3 planes, or NULL). */
+int oracle_capillary_force(int64_t nx, int64_t ny, int64_t nz, const double* phi, double sigma,
+                           double W, const double* Fb, double* F) {
+  const int64_t N = nx * ny * nz;
+  double* g = malloc(sizeof(double) * 3 * N);
+  double* l = malloc(sizeof(double) * N);
+  int rc = (g && l) ? 0 : -1;
+  const double beta = 12.0 * sigma / W, kappa = 1.5 * sigma * W;
+  if (!rc) rc = oracle_grad(nx, ny, nz, phi, g);
+  if (!rc) rc = oracle_lap(nx, ny, nz, phi, l);
+  if (!rc)
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < N; ++s) {
+      const double p = phi[s];
+      const double mu = 4.0 * beta * p * (p - 1.0) * (p - 0.5) - kappa * l[s];
+      for (int a = 0; a < 3; ++a) F[a * N + s] = mu * g[a * N + s] + (Fb ? Fb[a * N + s] : 0.0);
+    }
+  free(g); free(l);
+  return rc;
+}
