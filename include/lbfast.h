@@ -149,6 +149,38 @@ int lbfast_get_scales(lbfast_t h, float out[10]);
  * reproducible from run to run. */
 int lbfast_set_launch(lbfast_t h, int tile_rows, int z_chunk);
 
+/* Two-component variant (section 2): a phase field phi in [0, 1] (1: heavy
+ * phase) transported by the conservative Allen-Cahn equation, Eq. (2),
+ * advanced by forward-time centred-space differences with the D3Q27-weighted
+ * derivative stencils of section 2, and the capillary force
+ * F = mu grad(phi), mu = 4 beta phi (phi - 1)(phi - 1/2) - kappa lap(phi),
+ * beta = 12 sigma / W, kappa = 3 sigma W / 2, plus the uniform params.force.
+ * This build supports equal phase densities (rho_l = rho_h = 1) and
+ * viscosities (tau_l = tau_h = params.tau), where the pressure and viscous
+ * force terms vanish; other values give LBF_E_UNSUPPORTED.  Periodic grids
+ * only; no per-site force field.  Each lbfast_step then performs, in order:
+ * phi(t+1) from phi(t) and u(t); F(t+1) from phi(t+1); the fused step with
+ * F(t) at the sources and F(t+1) in the correction of Eq. (8).  FTCS is
+ * stable for diffusivity < ~0.34 with these stencils (not checked). */
+typedef struct lbfast_phase_params {
+  uint32_t struct_size; /* = sizeof(lbfast_phase_params) */
+  int32_t reserved0;    /* must be zero */
+  double sigma;         /* surface tension, >= 0 */
+  double width;         /* interface thickness W, > 0 */
+  double diffusivity;   /* D of Eq. (2), >= 0; lambda = 4 D / W */
+  double rho_l, rho_h;  /* phase densities: both 1 */
+  double tau_l, tau_h;  /* phase relaxation times: both params.tau */
+} lbfast_phase_params;
+
+/* Switch the handle to the two-component variant.  The library allocates
+ * (and frees at destroy) 11 x N values of the compute type: phi and F for two
+ * time levels, and the compression flux.  phi starts at 0. */
+int lbfast_enable_two_phase(lbfast_t h, const lbfast_phase_params* pp);
+/* Copy the phase field (N values, dtype LBF_F64 or LBF_F32, host or device)
+ * in or out.  set also computes the force of the current time level. */
+int lbfast_set_phase(lbfast_t h, const void* phi, int dtype, int on_device);
+int lbfast_get_phase(lbfast_t h, void* phi, int dtype, int on_device);
+
 /* Discrete adjoint (the paper does not treat differentiation; this is the
  * exact reverse mode of the discrete step of Eqs. (7)-(9) as implemented by
  * lbfast_step, for F64 and F32 storage; LBF_E_UNSUPPORTED for 16-bit).

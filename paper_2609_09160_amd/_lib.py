@@ -31,6 +31,13 @@ class LbfastParams(ctypes.Structure):
                 ("scale", ctypes.c_float * 10), ("reserved", ctypes.c_int32 * 8)]
 
 
+class LbfastPhaseParams(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("reserved0", ctypes.c_int32),
+                ("sigma", ctypes.c_double), ("width", ctypes.c_double),
+                ("diffusivity", ctypes.c_double), ("rho_l", ctypes.c_double),
+                ("rho_h", ctypes.c_double), ("tau_l", ctypes.c_double), ("tau_h", ctypes.c_double)]
+
+
 class LbfastError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
@@ -69,6 +76,9 @@ def load():
         "lbfast_set_launch": ([vp, i32, i32], i32),
         "lbfast_last_error": ([], ctypes.c_char_p),
         "lbfast_stream_probe": ([vp, vp, i64, i32, vp], i32),
+        "lbfast_enable_two_phase": ([vp, ctypes.POINTER(LbfastPhaseParams)], i32),
+        "lbfast_set_phase": ([vp, vp, i32, i32], i32),
+        "lbfast_get_phase": ([vp, vp, i32, i32], i32),
         "lbfast_forward_checkpointed": ([vp, i64, i64, vp], i32),
         "lbfast_adjoint_work_bytes": ([vp, i64], ctypes.c_size_t),
         "lbfast_adjoint": ([vp, i64, i64, vp, vp, vp, vp, vp], i32),

@@ -12,6 +12,8 @@ struct StepArgs {
   const void* src;     // current moment buffer (10 planes)
   void* dst;           // next moment buffer (10 planes)
   const void* Ffield;  // 3 planes of the compute type, or nullptr (uniform F)
+  const void* Fnext;   // force of the next time level for the correction, or
+                       // nullptr (static force: Ffield serves both)
   int nx, ny, nz;
   int64_t N;           // plane stride = nx*ny*nz
   int tiles_x, tiles_y, zchunks, zchunk;
@@ -36,6 +38,29 @@ hipError_t launch_step(int Q, int storage, int tile_rows, bool walls_y, const St
 // One step of the discrete adjoint (FP64 or FP32 storage only).
 hipError_t launch_adjoint(int Q, int storage, int tile_rows, bool walls_y, const StepArgs& a,
                           hipStream_t stream);
+
+// Two-component variant: arguments of the phase-field kernels (compute type
+// C = double for FP64 storage, float otherwise).
+struct PhaseArgs {
+  const void* phi;    // phi(t), N values of C
+  void* phi_out;      // phi(t+1)
+  const void* state;  // moment buffer at t (its velocity planes are read)
+  void* J;            // scratch: 3 planes of C (interface-compression flux)
+  void* F;            // receives F(t+1): 3 planes of C
+  int nx, ny, nz;
+  int64_t N;
+  double D, lambda, beta, kappa, eps;
+  double Fb[3];       // uniform body force added to the capillary force
+  float scale[10];    // storage scales (16-bit storage)
+};
+// phi_out = FTCS step of the Allen-Cahn equation from phi and the state's u
+hipError_t launch_phase_step(int storage, const PhaseArgs& a, hipStream_t stream);
+// F = mu(phi_out) grad(phi_out) + Fb
+hipError_t launch_capillary_force(int storage, const PhaseArgs& a, hipStream_t stream);
+// n values between a user array (F64 or F32) and the compute type of the storage:
+// dst_is_user = 0 converts user -> compute type, 1 compute type -> user
+hipError_t launch_convert(int storage, int user_dtype, const void* src, int dst_is_user,
+                          void* dst, int64_t n, hipStream_t stream);
 
 // zero nbytes bytes (a multiple of 4) with a kernel, so that graph capture
 // records no memset node

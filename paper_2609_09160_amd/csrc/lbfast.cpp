@@ -106,6 +106,12 @@ struct lbfast_ctx {
   bool scales_fixed = false;
   int tile_rows = 8;
   int z_chunk = 0;
+  bool two_phase = false;
+  lbfast_phase_params pp;
+  void* phi[2] = {nullptr, nullptr};  // phase field, two time levels
+  void* Fph[2] = {nullptr, nullptr};  // force of the two time levels (3 planes)
+  void* Jph = nullptr;                // compression flux (3 planes)
+  int pcur = 0;
   double* d_partials = nullptr;  // kReduceBlocks*5 + 5 doubles
   unsigned* d_maxbits = nullptr; // 10
   int64_t N = 0;
@@ -199,7 +205,33 @@ int launch_forward(const lbfast_ctx* h, const lbf::StepArgs& a) {
   return LBF_OK;
 }
 
+size_t compute_bytes(const lbfast_ctx* h) { return h->p.storage == LBF_F64 ? 8 : 4; }
+
+// phase-field launch arguments for the current time level
+lbf::PhaseArgs phase_args(const lbfast_ctx* h) {
+  lbf::PhaseArgs a{};
+  a.phi = h->phi[h->pcur];
+  a.phi_out = h->phi[h->pcur ^ 1];
+  a.state = h->buf[h->cur];
+  a.J = h->Jph;
+  a.F = h->Fph[h->pcur ^ 1];
+  a.nx = static_cast<int>(h->p.nx);
+  a.ny = static_cast<int>(h->p.ny);
+  a.nz = static_cast<int>(h->p.nz);
+  a.N = h->N;
+  a.D = h->pp.diffusivity;
+  a.lambda = 4.0 * h->pp.diffusivity / h->pp.width;
+  a.beta = 12.0 * h->pp.sigma / h->pp.width;
+  a.kappa = 1.5 * h->pp.sigma * h->pp.width;
+  a.eps = 1e-12;  // n = grad(phi) / (|grad(phi)| + eps)
+  for (int k = 0; k < 3; ++k) a.Fb[k] = h->p.force[k];
+  for (int k = 0; k < 10; ++k) a.scale[k] = h->scale[k];
+  return a;
+}
+
 int check_adjoint_args(const lbfast_ctx* h, int64_t nsteps, int64_t every) {
+  if (h->two_phase)
+    return fail(LBF_E_UNSUPPORTED, "the adjoint does not cover the two-component variant");
   if (h->p.storage != LBF_F64 && h->p.storage != LBF_F32)
     return fail(LBF_E_UNSUPPORTED, "the adjoint supports F64 and F32 storage only");
   if (nsteps < 0) return fail(LBF_E_ARG, "nsteps must be >= 0");
@@ -308,6 +340,8 @@ int lbfast_destroy(lbfast_t h) {
     if (h->buf[0]) (void)hipFree(h->buf[0]);
     if (h->buf[1]) (void)hipFree(h->buf[1]);
   }
+  for (void* p : {h->phi[0], h->phi[1], h->Fph[0], h->Fph[1], h->Jph})
+    if (p) (void)hipFree(p);
   if (h->d_partials) (void)hipFree(h->d_partials);
   if (h->d_maxbits) (void)hipFree(h->d_maxbits);
   delete h;
@@ -440,6 +474,8 @@ int lbfast_get_moments(lbfast_t h, void* m, int dtype, int on_device) {
 int lbfast_set_force_field(lbfast_t h, const void* F_dev, int dtype) {
   g_err.clear();
   if (int rc = check_handle(h)) return rc;
+  if (h->two_phase)
+    return fail(LBF_E_STATE, "the two-component variant computes its own force field");
   if (!F_dev) {
     h->Ffield = nullptr;
     return LBF_OK;
@@ -484,9 +520,139 @@ int lbfast_step(lbfast_t h, int64_t n) {
   for (int64_t s = 0; s < n; ++s) {
     a.src = h->buf[h->cur];
     a.dst = h->buf[h->cur ^ 1];
+    if (h->two_phase) {
+      // phi(t+1) and F(t+1) first: the correction needs the new force
+      lbf::PhaseArgs pa = phase_args(h);
+      hipError_t e = lbf::launch_phase_step(h->p.storage, pa, h->stream);
+      if (e == hipSuccess) e = lbf::launch_capillary_force(h->p.storage, pa, h->stream);
+      if (e != hipSuccess) return hip_fail(e, "phase-field launch");
+      a.Ffield = h->Fph[h->pcur];
+      a.Fnext = h->Fph[h->pcur ^ 1];
+    }
     if (int rc = launch_forward(h, a)) return rc;
     h->cur ^= 1;
+    if (h->two_phase) h->pcur ^= 1;
   }
+  return LBF_OK;
+}
+
+int lbfast_enable_two_phase(lbfast_t h, const lbfast_phase_params* pp) {
+  g_err.clear();
+  if (int rc = check_handle(h)) return rc;
+  if (!pp) return fail(LBF_E_ARG, "phase params is NULL");
+  if (pp->struct_size != sizeof(lbfast_phase_params))
+    return fail(LBF_E_ARG, "phase params struct_size = %u, expected %zu", pp->struct_size,
+                sizeof(lbfast_phase_params));
+  if (pp->reserved0 != 0) return fail(LBF_E_ARG, "reserved0 must be zero");
+  if (!std::isfinite(pp->sigma) || pp->sigma < 0) return fail(LBF_E_ARG, "sigma must be >= 0");
+  if (!std::isfinite(pp->width) || !(pp->width > 0)) return fail(LBF_E_ARG, "width must be > 0");
+  if (!std::isfinite(pp->diffusivity) || pp->diffusivity < 0)
+    return fail(LBF_E_ARG, "diffusivity must be >= 0");
+  if (pp->rho_l != 1.0 || pp->rho_h != 1.0)
+    return fail(LBF_E_UNSUPPORTED, "density contrast is not built: rho_l = rho_h = 1 required");
+  if (pp->tau_l != h->p.tau || pp->tau_h != h->p.tau)
+    return fail(LBF_E_UNSUPPORTED, "viscosity contrast is not built: tau_l = tau_h = tau required");
+  for (int ax = 0; ax < 3; ++ax)
+    if (h->p.bc[ax] != LBF_PERIODIC)
+      return fail(LBF_E_UNSUPPORTED, "the two-component variant needs a periodic grid");
+  if (h->Ffield) return fail(LBF_E_STATE, "a per-site force field is set");
+  if (h->two_phase) return fail(LBF_E_STATE, "two-component variant already enabled");
+  DeviceGuard g(h->device);
+  const size_t c = compute_bytes(h);
+  const size_t pb = static_cast<size_t>(h->N) * c;
+  hipError_t e = hipSuccess;
+  void** slots[5] = {&h->phi[0], &h->phi[1], &h->Fph[0], &h->Fph[1], &h->Jph};
+  const size_t sizes[5] = {pb, pb, 3 * pb, 3 * pb, 3 * pb};
+  for (int i = 0; i < 5 && e == hipSuccess; ++i) e = hipMalloc(slots[i], sizes[i]);
+  for (int i = 0; i < 5 && e == hipSuccess; ++i)
+    e = lbf::launch_zero(*slots[i], static_cast<int64_t>(sizes[i]), h->stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    for (int i = 0; i < 5; ++i)
+      if (*slots[i]) {
+        (void)hipFree(*slots[i]);
+        *slots[i] = nullptr;
+      }
+    return fail(LBF_E_NOMEM, "two-component buffers: %s", hipGetErrorString(e));
+  }
+  h->pp = *pp;
+  h->two_phase = true;
+  h->pcur = 0;
+  // F(0) of phi = 0: the body force alone
+  lbf::PhaseArgs pa = phase_args(h);
+  pa.phi_out = h->phi[0];
+  pa.F = h->Fph[0];
+  e = lbf::launch_capillary_force(h->p.storage, pa, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "capillary force");
+  return LBF_OK;
+}
+
+int lbfast_set_phase(lbfast_t h, const void* phi, int dtype, int on_device) {
+  g_err.clear();
+  if (int rc = check_handle(h)) return rc;
+  if (!h->two_phase) return fail(LBF_E_STATE, "two-component variant not enabled");
+  if (!phi) return fail(LBF_E_ARG, "phi is NULL");
+  if (dtype != LBF_F64 && dtype != LBF_F32) return fail(LBF_E_ARG, "dtype must be F64 or F32");
+  if (on_device != 0 && on_device != 1) return fail(LBF_E_ARG, "on_device must be 0 or 1");
+  DeviceGuard g(h->device);
+  const size_t ub = (dtype == LBF_F64) ? 8 : 4;
+  const size_t bytes = static_cast<size_t>(h->N) * ub;
+  const void* src = phi;
+  void* staging = nullptr;
+  hipError_t e = hipSuccess;
+  if (!on_device) {
+    e = hipMalloc(&staging, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(LBF_E_NOMEM, "staging allocation failed");
+    }
+    e = hipMemcpyAsync(staging, phi, bytes, hipMemcpyHostToDevice, h->stream);
+    src = staging;
+  }
+  if (e == hipSuccess)
+    e = lbf::launch_convert(h->p.storage, dtype, src, 0, h->phi[h->pcur], h->N, h->stream);
+  if (e == hipSuccess) {
+    lbf::PhaseArgs pa = phase_args(h);
+    pa.phi_out = h->phi[h->pcur];
+    pa.F = h->Fph[h->pcur];
+    e = lbf::launch_capillary_force(h->p.storage, pa, h->stream);
+  }
+  if (staging) {
+    hipError_t e2 = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = e2;
+    (void)hipFree(staging);
+  }
+  if (e != hipSuccess) return hip_fail(e, "set_phase");
+  return LBF_OK;
+}
+
+int lbfast_get_phase(lbfast_t h, void* phi, int dtype, int on_device) {
+  g_err.clear();
+  if (int rc = check_handle(h)) return rc;
+  if (!h->two_phase) return fail(LBF_E_STATE, "two-component variant not enabled");
+  if (!phi) return fail(LBF_E_ARG, "phi is NULL");
+  if (dtype != LBF_F64 && dtype != LBF_F32) return fail(LBF_E_ARG, "dtype must be F64 or F32");
+  if (on_device != 0 && on_device != 1) return fail(LBF_E_ARG, "on_device must be 0 or 1");
+  DeviceGuard g(h->device);
+  const size_t ub = (dtype == LBF_F64) ? 8 : 4;
+  const size_t bytes = static_cast<size_t>(h->N) * ub;
+  void* dst = phi;
+  void* staging = nullptr;
+  hipError_t e = hipSuccess;
+  if (!on_device) {
+    e = hipMalloc(&staging, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(LBF_E_NOMEM, "staging allocation failed");
+    }
+    dst = staging;
+  }
+  e = lbf::launch_convert(h->p.storage, dtype, h->phi[h->pcur], 1, dst, h->N, h->stream);
+  if (e == hipSuccess && staging)
+    e = hipMemcpyAsync(phi, staging, bytes, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (staging) (void)hipFree(staging);
+  if (e != hipSuccess) return hip_fail(e, "get_phase");
   return LBF_OK;
 }
 

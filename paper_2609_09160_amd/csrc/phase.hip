@@ -1,0 +1,250 @@
+// phase.hip -- the phase field of the two-component variant (paper, section
+// 2): the conservative Allen-Cahn equation, Eq. (2), advanced by
+// forward-time centred-space differences, and the capillary force
+// F^s = mu grad(phi), mu = 4 beta phi (phi - 1)(phi - 1/2) - kappa lap(phi),
+// beta = 12 sigma / W, kappa = 3 sigma W / 2.  With equal phase densities
+// and viscosities the pressure and viscous force terms vanish, so the total
+// force is F^s plus the uniform body force.
+//
+// Derivatives use the D3Q27-weighted stencils of section 2 (weights
+// k_i / 216 with k = 64, 16, 4, 1 for |c|^2 = 0..3):
+//   grad_a Psi = (1/cs^2) sum_i w_i c_ia Psi(x + c_i)   = (1/72) sum k_i c_ia Psi_i
+//   lap Psi    = (2/cs^2) sum_{i!=0} w_i (Psi_i - Psi_0) = (1/36) sum k_i (Psi_i - Psi_0)
+//   div V      = (1/cs^2) sum_i w_i c_i . V(x + c_i)
+// (the printed Laplacian stencil is garbled; this is its Taylor-consistent
+// reading, zero on constants).  Periodic grid.
+//
+// One thread per site; the 26 neighbours are read through the caches (these
+// kernels move 16 + 32 + 16 B per lattice update at FP32 against the
+// step's 104).
+#include "internal.hpp"
+#include "lattice.hpp"
+
+namespace lbf {
+namespace {
+
+constexpr int kPhaseThreads = 256;
+
+// D3Q27 stencil weight numerators (w = k / 216) by |c|^2
+__device__ constexpr int k27(int dx, int dy, int dz) {
+  const int c2 = dx * dx + dy * dy + dz * dz;
+  return c2 == 0 ? 64 : (c2 == 1 ? 16 : (c2 == 2 ? 4 : 1));
+}
+
+// periodic neighbour offsets of site (x, y, z): ox[d+1] etc.
+struct Nbr {
+  int64_t ox[3], oy[3], oz[3];
+  int64_t s;
+};
+
+__device__ __forceinline__ Nbr neighbours(int64_t s, int nx, int ny, int nz) {
+  Nbr n;
+  const int64_t plane = static_cast<int64_t>(nx) * ny;
+  const int z = static_cast<int>(s / plane);
+  const int64_t r = s - static_cast<int64_t>(z) * plane;
+  const int y = static_cast<int>(r / nx);
+  const int x = static_cast<int>(r - static_cast<int64_t>(y) * nx);
+  for (int d = -1; d <= 1; ++d) {
+    n.ox[d + 1] = wrap(x + d, nx);
+    n.oy[d + 1] = static_cast<int64_t>(wrap(y + d, ny)) * nx;
+    n.oz[d + 1] = static_cast<int64_t>(wrap(z + d, nz)) * plane;
+  }
+  n.s = s;
+  return n;
+}
+
+__device__ __forceinline__ int64_t at(const Nbr& n, int dx, int dy, int dz) {
+  return n.ox[dx + 1] + n.oy[dy + 1] + n.oz[dz + 1];
+}
+
+// grad and lap of a scalar field at one site
+template <typename C>
+__device__ __forceinline__ void grad_lap(const C* __restrict__ f, const Nbr& n, C g[3], C& lap) {
+  const C f0 = f[n.s];
+  C gx = 0, gy = 0, gz = 0, l = 0;
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        if (dx == 0 && dy == 0 && dz == 0) continue;
+        const C v = f[at(n, dx, dy, dz)];
+        const C k = C(k27(dx, dy, dz));
+        gx += C(dx) * k * v;
+        gy += C(dy) * k * v;
+        gz += C(dz) * k * v;
+        l += k * (v - f0);
+      }
+  g[0] = div_by<72>(gx);
+  g[1] = div_by<72>(gy);
+  g[2] = div_by<72>(gz);
+  lap = div_by<36>(l);
+}
+
+// normalised interface-compression flux J = phi (1 - phi) grad(phi) / (|grad phi| + eps)
+template <typename C>
+__global__ void __launch_bounds__(kPhaseThreads) flux_kernel(const C* __restrict__ phi,
+                                                             C* __restrict__ J, int nx, int ny,
+                                                             int nz, int64_t N, C eps) {
+  for (int64_t s = blockIdx.x * static_cast<int64_t>(kPhaseThreads) + threadIdx.x; s < N;
+       s += static_cast<int64_t>(gridDim.x) * kPhaseThreads) {
+    const Nbr n = neighbours(s, nx, ny, nz);
+    C g[3], l;
+    grad_lap(phi, n, g, l);
+    const C p = phi[s];
+    const C c = p * (C(1) - p) / (sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + eps);
+    J[s] = c * g[0];
+    J[N + s] = c * g[1];
+    J[2 * N + s] = c * g[2];
+  }
+}
+
+// phi' = phi - div(phi u) + D lap(phi) - lambda div(J), u from the state
+template <int ST>
+__global__ void __launch_bounds__(kPhaseThreads) update_kernel(
+    const typename Storage<ST>::C* __restrict__ phi, const typename Storage<ST>::T* __restrict__ st,
+    const typename Storage<ST>::C* __restrict__ J, typename Storage<ST>::C* __restrict__ out, int nx,
+    int ny, int nz, int64_t N, typename Storage<ST>::C D, typename Storage<ST>::C lambda, float s1,
+    float s2, float s3) {
+  using S = Storage<ST>;
+  using C = typename S::C;
+  const typename S::T* u[3] = {st + N, st + 2 * N, st + 3 * N};
+  const float sc[3] = {s1, s2, s3};
+  for (int64_t s = blockIdx.x * static_cast<int64_t>(kPhaseThreads) + threadIdx.x; s < N;
+       s += static_cast<int64_t>(gridDim.x) * kPhaseThreads) {
+    const Nbr n = neighbours(s, nx, ny, nz);
+    const C p0 = phi[s];
+    C adv = 0, comp = 0, l = 0;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          if (dx == 0 && dy == 0 && dz == 0) continue;
+          const int64_t i = at(n, dx, dy, dz);
+          const C k = C(k27(dx, dy, dz));
+          const C pi = phi[i];
+          C cu = 0, cJ = 0;
+          if (dx) {
+            cu += C(dx) * S::load(u[0], i, sc[0]);
+            cJ += C(dx) * J[i];
+          }
+          if (dy) {
+            cu += C(dy) * S::load(u[1], i, sc[1]);
+            cJ += C(dy) * J[N + i];
+          }
+          if (dz) {
+            cu += C(dz) * S::load(u[2], i, sc[2]);
+            cJ += C(dz) * J[2 * N + i];
+          }
+          adv += k * pi * cu;
+          comp += k * cJ;
+          l += k * (pi - p0);
+        }
+    out[s] = p0 - div_by<72>(adv) + D * div_by<36>(l) - lambda * div_by<72>(comp);
+  }
+}
+
+// F = mu grad(phi) + Fb
+template <typename C>
+__global__ void __launch_bounds__(kPhaseThreads) force_kernel(const C* __restrict__ phi,
+                                                              C* __restrict__ F, int nx, int ny,
+                                                              int nz, int64_t N, C beta, C kappa,
+                                                              C Fbx, C Fby, C Fbz) {
+  for (int64_t s = blockIdx.x * static_cast<int64_t>(kPhaseThreads) + threadIdx.x; s < N;
+       s += static_cast<int64_t>(gridDim.x) * kPhaseThreads) {
+    const Nbr n = neighbours(s, nx, ny, nz);
+    C g[3], l;
+    grad_lap(phi, n, g, l);
+    const C p = phi[s];
+    const C mu = C(4) * beta * p * (p - C(1)) * (p - C(0.5)) - kappa * l;
+    F[s] = mu * g[0] + Fbx;
+    F[N + s] = mu * g[1] + Fby;
+    F[2 * N + s] = mu * g[2] + Fbz;
+  }
+}
+
+int phase_grid(int64_t N) {
+  const int64_t b = (N + kPhaseThreads - 1) / kPhaseThreads;
+  return static_cast<int>(b < 16384 ? (b < 1 ? 1 : b) : 16384);
+}
+
+template <int ST>
+hipError_t phase_step_st(const PhaseArgs& a, hipStream_t s) {
+  using C = typename Storage<ST>::C;
+  using T = typename Storage<ST>::T;
+  const dim3 grid(phase_grid(a.N)), block(kPhaseThreads);
+  hipLaunchKernelGGL((flux_kernel<C>), grid, block, 0, s, static_cast<const C*>(a.phi),
+                     static_cast<C*>(a.J), a.nx, a.ny, a.nz, a.N, static_cast<C>(a.eps));
+  hipLaunchKernelGGL((update_kernel<ST>), grid, block, 0, s, static_cast<const C*>(a.phi),
+                     static_cast<const T*>(a.state), static_cast<const C*>(a.J),
+                     static_cast<C*>(a.phi_out), a.nx, a.ny, a.nz, a.N, static_cast<C>(a.D),
+                     static_cast<C>(a.lambda), a.scale[1], a.scale[2], a.scale[3]);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_phase_step(int storage, const PhaseArgs& a, hipStream_t s) {
+  switch (storage) {
+    case kF64: return phase_step_st<kF64>(a, s);
+    case kF32: return phase_step_st<kF32>(a, s);
+    case kF16S: return phase_step_st<kF16S>(a, s);
+    case kBF16S: return phase_step_st<kBF16S>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_capillary_force(int storage, const PhaseArgs& a, hipStream_t s) {
+  const dim3 grid(phase_grid(a.N)), block(kPhaseThreads);
+  if (storage == kF64) {
+    hipLaunchKernelGGL((force_kernel<double>), grid, block, 0, s,
+                       static_cast<const double*>(a.phi_out), static_cast<double*>(a.F), a.nx,
+                       a.ny, a.nz, a.N, a.beta, a.kappa, a.Fb[0], a.Fb[1], a.Fb[2]);
+  } else {
+    hipLaunchKernelGGL((force_kernel<float>), grid, block, 0, s,
+                       static_cast<const float*>(a.phi_out), static_cast<float*>(a.F), a.nx,
+                       a.ny, a.nz, a.N, static_cast<float>(a.beta), static_cast<float>(a.kappa),
+                       static_cast<float>(a.Fb[0]), static_cast<float>(a.Fb[1]),
+                       static_cast<float>(a.Fb[2]));
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lbf
+
+namespace lbf {
+namespace {
+
+template <typename From, typename To>
+__global__ void convert_kernel(const From* __restrict__ src, To* __restrict__ dst, int64_t n) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kPhaseThreads) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kPhaseThreads)
+    dst[i] = static_cast<To>(src[i]);
+}
+
+template <typename A, typename B>
+hipError_t convert_t(const void* src, void* dst, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((convert_kernel<A, B>), dim3(phase_grid(n)), dim3(kPhaseThreads), 0, s,
+                     static_cast<const A*>(src), static_cast<B*>(dst), n);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// dst_is_user = 0: user (src_dtype) -> compute type of the storage;
+// dst_is_user = 1: compute type -> user (src_dtype names the user type)
+hipError_t launch_convert(int storage, int user_dtype, const void* src, int dst_is_user, void* dst,
+                          int64_t n, hipStream_t s) {
+  const bool c64 = storage == kF64, u64 = user_dtype == kF64;
+  if (!dst_is_user) {
+    if (c64) return u64 ? convert_t<double, double>(src, dst, n, s) : convert_t<float, double>(src, dst, n, s);
+    return u64 ? convert_t<double, float>(src, dst, n, s) : convert_t<float, float>(src, dst, n, s);
+  }
+  if (c64) return u64 ? convert_t<double, double>(src, dst, n, s) : convert_t<double, float>(src, dst, n, s);
+  return u64 ? convert_t<float, double>(src, dst, n, s) : convert_t<float, float>(src, dst, n, s);
+}
+
+}  // namespace lbf

@@ -73,20 +73,25 @@ __device__ __forceinline__ void finalize(const Sums<C>& S, C Fx, C Fy, C Fz, C o
 
 // The forward step as a physics policy of the z-march: a site reads its 10
 // stored moments (and the force), its values are the post-collision
-// populations, and a destination writes its 10 new moments.
-template <int Q_, int ST, bool FFIELD>
+// populations, and a destination writes its 10 new moments.  FNEXT: the force
+// changes every step (two-component flow); the source uses F(t) and the
+// correction of Eq. (8) at the destination uses F(t+1) from a second field.
+template <int Q_, int ST, bool FFIELD, bool FNEXT = false>
 struct Forward {
+  static_assert(FFIELD || !FNEXT, "a time-dependent force is a force field");
   static constexpr int Q = Q_;
   using S = Storage<ST>;
   using C = typename S::C;
   using T = typename S::T;
-  // raw (still encoded) moments and force of one site, fetched a plane ahead
+  // raw (still encoded) moments and force of one site, fetched a plane ahead;
+  // destinations of a time-dependent force also fetch F(t+1)
   template <bool OWN>
   struct Raw {
     T m[10];
     C F[3];
+    C Fn[(FNEXT && OWN) ? 3 : 1];
   };
-  // force at the source site, needed again by the correction at the same site
+  // force of the correction at the site (F(t), or F(t+1) when it changes)
   struct Carry {
     C F[3];
   };
@@ -108,6 +113,12 @@ struct Forward {
       for (int k = 0; k < 3; ++k)
         r.F[k] = buf_load<C>(plane_rsrc(Ff + (k * a.N + pb), plane_bytes * kFscale), off * kFscale);
     }
+    if constexpr (FNEXT && OWN) {
+      const C* __restrict__ Fn = static_cast<const C*>(a.Fnext);
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        r.Fn[k] = buf_load<C>(plane_rsrc(Fn + (k * a.N + pb), plane_bytes * kFscale), off * kFscale);
+    }
   }
 
   template <bool OWN>
@@ -120,16 +131,17 @@ struct Forward {
 #pragma unroll
       for (int k = 4; k < 10; ++k) m[k] += m[1 + a2_a(k)] * m[1 + a2_b(k)];
     }
-    if constexpr (FFIELD) {
-      c.F[0] = r.F[0];
-      c.F[1] = r.F[1];
-      c.F[2] = r.F[2];
-    } else {
-      c.F[0] = static_cast<C>(a.F[0]);
-      c.F[1] = static_cast<C>(a.F[1]);
-      c.F[2] = static_cast<C>(a.F[2]);
+    C F[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) F[k] = FFIELD ? r.F[k] : static_cast<C>(a.F[k]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if constexpr (FNEXT && OWN)
+        c.F[k] = r.Fn[k];
+      else
+        c.F[k] = F[k];
     }
-    source_pops<Q, C>(m, c.F[0], c.F[1], c.F[2], static_cast<C>(a.omega), g);
+    source_pops<Q, C>(m, F[0], F[1], F[2], static_cast<C>(a.omega), g);
   }
 
   static __device__ __forceinline__ void finish(const StepArgs& a, const Sums<C>& acc,
@@ -155,6 +167,11 @@ struct Forward {
 
 template <int Q, int ST, int TY, bool WALLY, bool FFIELD>
 hipError_t launch_step_t(const StepArgs& a, hipStream_t stream) {
+  if constexpr (FFIELD && !WALLY) {
+    // a force that changes every step (two-component flow; periodic only)
+    if (a.Fnext) return launch_march<Forward<Q, ST, true, true>, TY, false>(a, stream);
+  }
+  if (a.Fnext) return hipErrorInvalidValue;
   return launch_march<Forward<Q, ST, FFIELD>, TY, WALLY>(a, stream);
 }
 

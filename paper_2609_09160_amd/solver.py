@@ -120,6 +120,40 @@ class Solver:
         check(rc)
         return np.array(out[:])
 
+    # -- two-component variant -------------------------------------------------------
+    def enable_two_phase(self, sigma, width, diffusivity, rho=(1.0, 1.0), tau=None):
+        """Phase field by the conservative Allen-Cahn equation plus capillary
+        force (equal densities and viscosities)."""
+        pp = _lib.LbfastPhaseParams()
+        pp.struct_size = ctypes.sizeof(_lib.LbfastPhaseParams)
+        pp.sigma, pp.width, pp.diffusivity = float(sigma), float(width), float(diffusivity)
+        pp.rho_l, pp.rho_h = (float(v) for v in rho)
+        t = self.params.tau if tau is None else tau
+        pp.tau_l, pp.tau_h = (float(v) for v in (t if np.ndim(t) else (t, t)))
+        check(self.lib.lbfast_enable_two_phase(self.h, ctypes.byref(pp)))
+
+    def set_phase(self, phi):
+        """phi: [nz, ny, nx] (or N) float64/float32, host or device."""
+        torch = self._torch
+        if isinstance(phi, np.ndarray):
+            phi = torch.from_numpy(np.ascontiguousarray(phi))
+        if phi.dtype not in (torch.float64, torch.float32) or phi.numel() != self.N:
+            raise ValueError("phi must be N float64/float32 values")
+        phi = phi.contiguous()
+        dt = _lib.LBF_F64 if phi.dtype == torch.float64 else _lib.LBF_F32
+        check(self.lib.lbfast_set_phase(self.h, ctypes.c_void_p(phi.data_ptr()), dt,
+                                        1 if phi.is_cuda else 0))
+        self.sync()
+
+    def phase(self, dtype=None):
+        """Current phase field as a device tensor [nz, ny, nx] (float64 default)."""
+        torch = self._torch
+        nx, ny, nz = self.shape
+        out = torch.empty((nz, ny, nx), dtype=dtype or torch.float64, device=self.device)
+        dt = _lib.LBF_F64 if out.dtype == torch.float64 else _lib.LBF_F32
+        check(self.lib.lbfast_get_phase(self.h, ctypes.c_void_p(out.data_ptr()), dt, 1))
+        return out
+
     # -- discrete adjoint ----------------------------------------------------------
     def buffer_bytes(self):
         return self._bufs[0].numel()
