@@ -187,6 +187,40 @@ def run_adjoint(n=192, steps=500, every=50, reps=2):
             "finite": finite}
 
 
+TP_BYTES_PER_LUP = 172  # two-component step, FP32: fused step with F(t) and F(t+1) 104;
+                        # phase flux 32 (phi, u in; flux and phi record out); phase
+                        # update 20 (record in; phi out); capillary force 16 (phi in, F out)
+
+
+def run_two_phase(n=256, steps=100, warmup=10, storage="f32"):
+    """Two-component workload: D3Q19 n^3 periodic, static droplet R = 40
+    centred, W = 4, sigma = 0.03, D = 0.1, equal densities, tau = 1."""
+    import torch
+    from paper_2609_09160_amd import Solver
+    shape = (n, n, n)
+    z, y, x = (torch.arange(n, device="cuda", dtype=torch.float64).view(*v)
+               for v in ((n, 1, 1), (1, n, 1), (1, 1, n)))
+    r = torch.sqrt((x - n / 2) ** 2 + (y - n / 2) ** 2 + (z - n / 2) ** 2)
+    phi = 0.5 * (1.0 - torch.tanh(2.0 * (r - 40.0) / 4.0))
+    s = Solver(shape, 1.0, storage=storage,
+               scale=None if storage in ("f32", "f64") else [2.0 ** -20] * 10)
+    s.enable_two_phase(0.03, 4.0, 0.1)
+    s.set_moments(torch.zeros((10, n, n, n), dtype=torch.float64, device="cuda"))
+    s.set_phase(phi)
+    del phi, r
+    ms = time_steps(s, steps, warmup)
+    s.reduce()  # raises if the state went non-finite
+    s.close()
+    torch.cuda.empty_cache()
+    sites = n ** 3
+    gbs = TP_BYTES_PER_LUP * sites / (ms * 1e-3) / 1e9
+    return {"mlups": round(sites / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
+            "workload": f"D3Q19 {storage.upper()} {n}^3 periodic, static droplet R=40 W=4 "
+                        "sigma=0.03 D=0.1, equal densities, tau=1",
+            "bytes_per_lup_algorithmic": TP_BYTES_PER_LUP,
+            "algorithmic_GBs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def cpu_baseline(lattice, budget_s=20.0):
     """The FP64 CPU oracle on the host cores, bounded sample of the workload."""
     import numpy as np
@@ -301,6 +335,8 @@ def main():
         out["variants"] = var
     if not args.no_adjoint:
         out["adjoint"] = run_adjoint()
+    if not args.no_variants:
+        out["two_phase"] = run_two_phase()
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         out["cpu_baseline"] = cpu_baseline(args.lattice)
     print(json.dumps(out), flush=True)

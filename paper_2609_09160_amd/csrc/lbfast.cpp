@@ -110,7 +110,7 @@ struct lbfast_ctx {
   lbfast_phase_params pp;
   void* phi[2] = {nullptr, nullptr};  // phase field, two time levels
   void* Fph[2] = {nullptr, nullptr};  // force of the two time levels (3 planes)
-  void* Jph = nullptr;                // compression flux (3 planes)
+  void* Jph = nullptr;                // phase-flux records (4 x N)
   int pcur = 0;
   double* d_partials = nullptr;  // kReduceBlocks*5 + 5 doubles
   unsigned* d_maxbits = nullptr; // 10
@@ -562,7 +562,7 @@ int lbfast_enable_two_phase(lbfast_t h, const lbfast_phase_params* pp) {
   const size_t pb = static_cast<size_t>(h->N) * c;
   hipError_t e = hipSuccess;
   void** slots[5] = {&h->phi[0], &h->phi[1], &h->Fph[0], &h->Fph[1], &h->Jph};
-  const size_t sizes[5] = {pb, pb, 3 * pb, 3 * pb, 3 * pb};
+  const size_t sizes[5] = {pb, pb, 3 * pb, 3 * pb, 4 * pb};
   for (int i = 0; i < 5 && e == hipSuccess; ++i) e = hipMalloc(slots[i], sizes[i]);
   for (int i = 0; i < 5 && e == hipSuccess; ++i)
     e = lbf::launch_zero(*slots[i], static_cast<int64_t>(sizes[i]), h->stream);

@@ -14,9 +14,12 @@
 // (the printed Laplacian stencil is garbled; this is its Taylor-consistent
 // reading, zero on constants).  Periodic grid.
 //
-// One thread per site; the 26 neighbours are read through the caches (these
-// kernels move 16 + 32 + 16 B per lattice update at FP32 against the
-// step's 104).
+// Two passes per step advance phi: the total flux V = phi u + lambda J (J the
+// normalised compression flux) at every site, stored with phi as one 4-wide
+// record, then phi' = phi - div(V) + D lap(phi).  One thread per site; the 26
+// neighbours are read through the caches.  Algorithmic traffic at FP32: flux
+// 32 B per lattice update (phi, u in; record out), update 20 B (record in;
+// phi out), force 16 B (phi in, F out), against the fused step's 104.
 #include "internal.hpp"
 #include "lattice.hpp"
 
@@ -82,40 +85,48 @@ __device__ __forceinline__ void grad_lap(const C* __restrict__ f, const Nbr& n, 
   lap = div_by<36>(l);
 }
 
-// normalised interface-compression flux J = phi (1 - phi) grad(phi) / (|grad phi| + eps)
+// per-site record of the update pass: the total phase flux
+// V = phi u + lambda phi (1 - phi) grad(phi) / (|grad phi| + eps) (advection plus
+// interface compression, so that Eq. (2) reads phi' = phi - div(V) + D lap(phi))
+// and phi itself, interleaved so that a neighbour is one 4-wide load
 template <typename C>
-__global__ void __launch_bounds__(kPhaseThreads) flux_kernel(const C* __restrict__ phi,
-                                                             C* __restrict__ J, int nx, int ny,
-                                                             int nz, int64_t N, C eps) {
+struct alignas(4 * sizeof(C)) Rec {
+  C vx, vy, vz, phi;
+};
+
+template <int ST>
+__global__ void __launch_bounds__(kPhaseThreads) flux_kernel(
+    const typename Storage<ST>::C* __restrict__ phi, const typename Storage<ST>::T* __restrict__ st,
+    Rec<typename Storage<ST>::C>* __restrict__ V, int nx, int ny, int nz, int64_t N,
+    typename Storage<ST>::C lambda, typename Storage<ST>::C eps, float s1, float s2, float s3) {
+  using S = Storage<ST>;
+  using C = typename S::C;
   for (int64_t s = blockIdx.x * static_cast<int64_t>(kPhaseThreads) + threadIdx.x; s < N;
        s += static_cast<int64_t>(gridDim.x) * kPhaseThreads) {
     const Nbr n = neighbours(s, nx, ny, nz);
     C g[3], l;
     grad_lap(phi, n, g, l);
     const C p = phi[s];
-    const C c = p * (C(1) - p) / (sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + eps);
-    J[s] = c * g[0];
-    J[N + s] = c * g[1];
-    J[2 * N + s] = c * g[2];
+    const C c = lambda * p * (C(1) - p) / (sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + eps);
+    Rec<C> r;
+    r.vx = p * S::load(st + N, s, s1) + c * g[0];
+    r.vy = p * S::load(st + 2 * N, s, s2) + c * g[1];
+    r.vz = p * S::load(st + 3 * N, s, s3) + c * g[2];
+    r.phi = p;
+    V[s] = r;
   }
 }
 
-// phi' = phi - div(phi u) + D lap(phi) - lambda div(J), u from the state
-template <int ST>
-__global__ void __launch_bounds__(kPhaseThreads) update_kernel(
-    const typename Storage<ST>::C* __restrict__ phi, const typename Storage<ST>::T* __restrict__ st,
-    const typename Storage<ST>::C* __restrict__ J, typename Storage<ST>::C* __restrict__ out, int nx,
-    int ny, int nz, int64_t N, typename Storage<ST>::C D, typename Storage<ST>::C lambda, float s1,
-    float s2, float s3) {
-  using S = Storage<ST>;
-  using C = typename S::C;
-  const typename S::T* u[3] = {st + N, st + 2 * N, st + 3 * N};
-  const float sc[3] = {s1, s2, s3};
+// phi' = phi - div(V) + D lap(phi)
+template <typename C>
+__global__ void __launch_bounds__(kPhaseThreads) update_kernel(const Rec<C>* __restrict__ V,
+                                                               C* __restrict__ out, int nx, int ny,
+                                                               int nz, int64_t N, C D) {
   for (int64_t s = blockIdx.x * static_cast<int64_t>(kPhaseThreads) + threadIdx.x; s < N;
        s += static_cast<int64_t>(gridDim.x) * kPhaseThreads) {
     const Nbr n = neighbours(s, nx, ny, nz);
-    const C p0 = phi[s];
-    C adv = 0, comp = 0, l = 0;
+    const C p0 = V[s].phi;
+    C dv = 0, l = 0;
 #pragma unroll
     for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
@@ -123,27 +134,16 @@ __global__ void __launch_bounds__(kPhaseThreads) update_kernel(
 #pragma unroll
         for (int dx = -1; dx <= 1; ++dx) {
           if (dx == 0 && dy == 0 && dz == 0) continue;
-          const int64_t i = at(n, dx, dy, dz);
+          const Rec<C> r = V[at(n, dx, dy, dz)];
           const C k = C(k27(dx, dy, dz));
-          const C pi = phi[i];
-          C cu = 0, cJ = 0;
-          if (dx) {
-            cu += C(dx) * S::load(u[0], i, sc[0]);
-            cJ += C(dx) * J[i];
-          }
-          if (dy) {
-            cu += C(dy) * S::load(u[1], i, sc[1]);
-            cJ += C(dy) * J[N + i];
-          }
-          if (dz) {
-            cu += C(dz) * S::load(u[2], i, sc[2]);
-            cJ += C(dz) * J[2 * N + i];
-          }
-          adv += k * pi * cu;
-          comp += k * cJ;
-          l += k * (pi - p0);
+          C cv = 0;
+          if (dx) cv += C(dx) * r.vx;
+          if (dy) cv += C(dy) * r.vy;
+          if (dz) cv += C(dz) * r.vz;
+          dv += k * cv;
+          l += k * (r.phi - p0);
         }
-    out[s] = p0 - div_by<72>(adv) + D * div_by<36>(l) - lambda * div_by<72>(comp);
+    out[s] = p0 - div_by<72>(dv) + D * div_by<36>(l);
   }
 }
 
@@ -176,12 +176,12 @@ hipError_t phase_step_st(const PhaseArgs& a, hipStream_t s) {
   using C = typename Storage<ST>::C;
   using T = typename Storage<ST>::T;
   const dim3 grid(phase_grid(a.N)), block(kPhaseThreads);
-  hipLaunchKernelGGL((flux_kernel<C>), grid, block, 0, s, static_cast<const C*>(a.phi),
-                     static_cast<C*>(a.J), a.nx, a.ny, a.nz, a.N, static_cast<C>(a.eps));
-  hipLaunchKernelGGL((update_kernel<ST>), grid, block, 0, s, static_cast<const C*>(a.phi),
-                     static_cast<const T*>(a.state), static_cast<const C*>(a.J),
-                     static_cast<C*>(a.phi_out), a.nx, a.ny, a.nz, a.N, static_cast<C>(a.D),
-                     static_cast<C>(a.lambda), a.scale[1], a.scale[2], a.scale[3]);
+  hipLaunchKernelGGL((flux_kernel<ST>), grid, block, 0, s, static_cast<const C*>(a.phi),
+                     static_cast<const T*>(a.state), static_cast<Rec<C>*>(a.J), a.nx, a.ny, a.nz,
+                     a.N, static_cast<C>(a.lambda), static_cast<C>(a.eps), a.scale[1], a.scale[2],
+                     a.scale[3]);
+  hipLaunchKernelGGL((update_kernel<C>), grid, block, 0, s, static_cast<const Rec<C>*>(a.J),
+                     static_cast<C*>(a.phi_out), a.nx, a.ny, a.nz, a.N, static_cast<C>(a.D));
   return hipGetLastError();
 }
 
