@@ -141,13 +141,21 @@ int lbfast_state_ptr(lbfast_t h, void** dev_ptr);
 /* The 16-bit storage scales in use (10 floats); 1.0 for FP32/FP64. */
 int lbfast_get_scales(lbfast_t h, float out[10]);
 
-/* Launch shape: rows per tile (4, 6, 8 or 14; LBF_E_UNSUPPORTED if the
- * tile's LDS would exceed 160 KiB) and z-planes per workgroup (>= 1); 0 keeps
+/* Launch shape: rows per tile (4, 6, 8 or 14 -- at most 8 with two sites
+ * per lane; LBF_E_UNSUPPORTED if the tile's LDS would exceed 160 KiB) and z-planes per workgroup (>= 1); 0 keeps
  * the current value.  Every shape computes the same formulas per site; the
  * tile heights are separately compiled, so results may differ between shapes
  * in the last bits (floating-point contraction), while one shape is bitwise
  * reproducible from run to run. */
 int lbfast_set_launch(lbfast_t h, int tile_rows, int z_chunk);
+
+/* Consecutive x-sites per lane: 1 (64-wide tiles) or 2 (128-wide tiles, one
+ * 2-wide load or store per moment plane; needs an even nx and tiles of at
+ * most 8 rows).  The default is 2 where nx is even and at least 128.  If the
+ * current tile height does not fit the 160 KiB of LDS with the new setting,
+ * the tallest of 8, 6 and 4 rows that does is taken.  Same formulas per site;
+ * results may differ between settings in the last bits. */
+int lbfast_set_lane_sites(lbfast_t h, int sites);
 
 /* Two-component variant (section 2): a phase field phi in [0, 1] (1: heavy
  * phase) transported by the conservative Allen-Cahn equation, Eq. (2),

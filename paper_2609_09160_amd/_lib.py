@@ -74,6 +74,7 @@ def load():
         "lbfast_state_ptr": ([vp, ctypes.POINTER(vp)], i32),
         "lbfast_get_scales": ([vp, ctypes.POINTER(ctypes.c_float)], i32),
         "lbfast_set_launch": ([vp, i32, i32], i32),
+        "lbfast_set_lane_sites": ([vp, i32], i32),
         "lbfast_last_error": ([], ctypes.c_char_p),
         "lbfast_stream_probe": ([vp, vp, i64, i32, vp], i32),
         "lbfast_enable_two_phase": ([vp, ctypes.POINTER(LbfastPhaseParams)], i32),

@@ -62,18 +62,29 @@ struct Adjoint {
     for (int k = 0; k < 3; ++k) c.F[k] = c.u[k] = c.g[k] = C(0);
   }
 
-  template <bool OWN>
+  template <bool OWN, int NS>
   static __device__ __forceinline__ void fetch(const StepArgs& a, int64_t pb, uint32_t off,
-                                               uint32_t plane_bytes, Raw<OWN>& r) {
+                                               uint32_t plane_bytes, Raw<OWN> (&r)[NS]) {
+    auto load = [&](const C* base, C (&v)[NS]) __attribute__((always_inline)) {
+      buf_load_n<C, NS>(plane_rsrc(base, plane_bytes), off, v);
+    };
     const C* __restrict__ lam = static_cast<const C*>(a.src);
 #pragma unroll
-    for (int k = 0; k < 10; ++k)
-      r.l[k] = buf_load<C>(plane_rsrc(lam + (k * a.N + pb), plane_bytes), off);
+    for (int k = 0; k < 10; ++k) {
+      C v[NS];
+      load(lam + (k * a.N + pb), v);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) r[s].l[k] = v[s];
+    }
     if constexpr (FFIELD) {
       const C* __restrict__ Ff = static_cast<const C*>(a.Ffield);
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
-        r.F[k] = buf_load<C>(plane_rsrc(Ff + (k * a.N + pb), plane_bytes), off);
+      for (int k = 0; k < 3; ++k) {
+        C v[NS];
+        load(Ff + (k * a.N + pb), v);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) r[s].F[k] = v[s];
+      }
     }
     if constexpr (OWN) {
       const C* __restrict__ sn = static_cast<const C*>(a.state_new);
@@ -81,9 +92,16 @@ struct Adjoint {
       const C* __restrict__ gf = static_cast<const C*>(a.gF);
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        r.x[k] = buf_load<C>(plane_rsrc(sn + ((1 + k) * a.N + pb), plane_bytes), off);
-        r.x[3 + k] = buf_load<C>(plane_rsrc(so + ((1 + k) * a.N + pb), plane_bytes), off);
-        r.x[6 + k] = buf_load<C>(plane_rsrc(gf + (k * a.N + pb), plane_bytes), off);
+        C v[NS];
+        load(sn + ((1 + k) * a.N + pb), v);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) r[s].x[k] = v[s];
+        load(so + ((1 + k) * a.N + pb), v);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) r[s].x[3 + k] = v[s];
+        load(gf + (k * a.N + pb), v);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) r[s].x[6 + k] = v[s];
       }
     }
   }
@@ -115,62 +133,73 @@ struct Adjoint {
     }
   }
 
-  static __device__ __forceinline__ void finish(const StepArgs& a, const Sums<C>& S,
-                                                const Carry& c, int64_t pb, uint32_t off,
+  template <int NS>
+  static __device__ __forceinline__ void finish(const StepArgs& a, const Sums<C> (&acc)[NS],
+                                                const Carry (&cc)[NS], int64_t pb, uint32_t off,
                                                 uint32_t plane_bytes) {
     constexpr int D = Lat<Q>::D;
     const C h = C(0.5);
     const C om = static_cast<C>(a.omega);
-    // gradients with respect to the post-collision coefficients P0, P1, P2
-    const C q0 = div_by<D>(S.s0);
-    const C q1x = C(-3) * div_by<D>(S.jx);
-    const C q1y = C(-3) * div_by<D>(S.jy);
-    const C q1z = C(-3) * div_by<D>(S.jz);
-    const C qxx = div_by<2 * D>(C(3) * (C(3) * S.pxx - S.s0));
-    const C qyy = div_by<2 * D>(C(3) * (C(3) * S.pyy - S.s0));
-    const C qzz = div_by<2 * D>(C(3) * (C(3) * S.pzz - S.s0));
-    const C qxy = C(9) * div_by<D>(S.pxy);
-    const C qxz = C(9) * div_by<D>(S.pxz);
-    const C qyz = C(9) * div_by<D>(S.pyz);
-    const C ux = c.u[0], uy = c.u[1], uz = c.u[2];
-    const C Fx = c.F[0], Fy = c.F[1], Fz = c.F[2];
-    const C two_om = C(2) * om;
-    C out[13];
-    out[0] = q0;
-    out[1] = q1x + qxx * (two_om * ux + Fx) + qxy * (om * uy + h * Fy) + qxz * (om * uz + h * Fz);
-    out[2] = q1y + qyy * (two_om * uy + Fy) + qxy * (om * ux + h * Fx) + qyz * (om * uz + h * Fz);
-    out[3] = q1z + qzz * (two_om * uz + Fz) + qxz * (om * ux + h * Fx) + qyz * (om * uy + h * Fy);
     const C om1 = C(1) - om;
-    out[4] = om1 * qxx;
-    out[5] = om1 * qyy;
-    out[6] = om1 * qzz;
-    out[7] = om1 * qxy;
-    out[8] = om1 * qxz;
-    out[9] = om1 * qyz;
-    out[10] = c.g[0] + h * q1x + qxx * ux + h * (qxy * uy + qxz * uz);
-    out[11] = c.g[1] + h * q1y + qyy * uy + h * (qxy * ux + qyz * uz);
-    out[12] = c.g[2] + h * q1z + qzz * uz + h * (qxz * ux + qyz * uy);
+    const C two_om = C(2) * om;
+    C out[NS][13];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const Sums<C>& S = acc[s];
+      const Carry& c = cc[s];
+      // gradients with respect to the post-collision coefficients P0, P1, P2
+      const C q0 = div_by<D>(S.s0);
+      const C q1x = C(-3) * div_by<D>(S.jx);
+      const C q1y = C(-3) * div_by<D>(S.jy);
+      const C q1z = C(-3) * div_by<D>(S.jz);
+      const C qxx = div_by<2 * D>(C(3) * (C(3) * S.pxx - S.s0));
+      const C qyy = div_by<2 * D>(C(3) * (C(3) * S.pyy - S.s0));
+      const C qzz = div_by<2 * D>(C(3) * (C(3) * S.pzz - S.s0));
+      const C qxy = C(9) * div_by<D>(S.pxy);
+      const C qxz = C(9) * div_by<D>(S.pxz);
+      const C qyz = C(9) * div_by<D>(S.pyz);
+      const C ux = c.u[0], uy = c.u[1], uz = c.u[2];
+      const C Fx = c.F[0], Fy = c.F[1], Fz = c.F[2];
+      C* o = out[s];
+      o[0] = q0;
+      o[1] = q1x + qxx * (two_om * ux + Fx) + qxy * (om * uy + h * Fy) + qxz * (om * uz + h * Fz);
+      o[2] = q1y + qyy * (two_om * uy + Fy) + qxy * (om * ux + h * Fx) + qyz * (om * uz + h * Fz);
+      o[3] = q1z + qzz * (two_om * uz + Fz) + qxz * (om * ux + h * Fx) + qyz * (om * uy + h * Fy);
+      o[4] = om1 * qxx;
+      o[5] = om1 * qyy;
+      o[6] = om1 * qzz;
+      o[7] = om1 * qxy;
+      o[8] = om1 * qxz;
+      o[9] = om1 * qyz;
+      o[10] = c.g[0] + h * q1x + qxx * ux + h * (qxy * uy + qxz * uz);
+      o[11] = c.g[1] + h * q1y + qyy * uy + h * (qxy * ux + qyz * uz);
+      o[12] = c.g[2] + h * q1z + qzz * uz + h * (qxz * ux + qyz * uy);
+    }
     C* __restrict__ lam = static_cast<C*>(a.dst);
     C* __restrict__ gf = static_cast<C*>(a.gF);
 #pragma unroll
-    for (int k = 0; k < 10; ++k)
-      buf_store_nt<C>(out[k], plane_rsrc(lam + (k * a.N + pb), plane_bytes), off);
+    for (int k = 0; k < 13; ++k) {
+      C v[NS];
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-      buf_store_nt<C>(out[10 + k], plane_rsrc(gf + (k * a.N + pb), plane_bytes), off);
+      for (int s = 0; s < NS; ++s) v[s] = out[s][k];
+      C* base = k < 10 ? lam + (k * a.N + pb) : gf + ((k - 10) * a.N + pb);
+      buf_store_nt_n<C, NS>(v, plane_rsrc(base, plane_bytes), off);
+    }
   }
 };
 
 template <typename C>
 hipError_t launch_adjoint_type(int Q, int tile_rows, bool walls_y, bool ffield,
                                const StepArgs& a, hipStream_t s) {
+  if (a.lane_sites != 1) return hipErrorInvalidValue;
+// one site per lane: a destination reads 22 values, two per lane would spill
 #define LBF_ADJ_CASE(QQ, TYY)                                                         \
   if (Q == QQ && tile_rows == TYY) {                                                 \
     if (walls_y)                                                                     \
-      return ffield ? launch_march<Adjoint<QQ, C, true>, TYY, true>(a, s)            \
-                    : launch_march<Adjoint<QQ, C, false>, TYY, true>(a, s);          \
-    return ffield ? launch_march<Adjoint<QQ, C, true>, TYY, false>(a, s)             \
-                  : launch_march<Adjoint<QQ, C, false>, TYY, false>(a, s);           \
+      return ffield ? launch_march_s<Adjoint<QQ, C, true>, TYY, true, 1>(a, s)       \
+                    : launch_march_s<Adjoint<QQ, C, false>, TYY, true, 1>(a, s);     \
+    return ffield ? launch_march_s<Adjoint<QQ, C, true>, TYY, false, 1>(a, s)        \
+                  : launch_march_s<Adjoint<QQ, C, false>, TYY, false, 1>(a, s);      \
   }
   LBF_ADJ_CASE(19, 4)
   LBF_ADJ_CASE(19, 6)

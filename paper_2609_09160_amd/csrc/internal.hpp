@@ -17,6 +17,7 @@ struct StepArgs {
   int nx, ny, nz;
   int64_t N;           // plane stride = nx*ny*nz
   int tiles_x, tiles_y, zchunks, zchunk;
+  int lane_sites;      // consecutive x-sites per lane: 1, or 2 (even nx; tile width 128)
   double omega;
   double F[3];         // uniform force (used when Ffield == nullptr)
   float scale[10];     // 16-bit storage: value = scale * q

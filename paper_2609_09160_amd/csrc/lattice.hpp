@@ -133,6 +133,56 @@ __device__ __forceinline__ void buf_store_nt(V v, __amdgpu_buffer_rsrc_t r, uint
   }
 }
 
+// S consecutive values (S = 1 or 2) at byte offset off, one load instruction.
+// The builtin's result is bit-cast as a whole to a vector of the element type
+// before its elements are taken: taking elements of the builtin's own
+// integer-vector result directly was compiled (ROCm 7.2) into a load of the
+// first dword only, with that dword reused for every element.
+template <typename V, int S>
+__device__ __forceinline__ void buf_load_n(__amdgpu_buffer_rsrc_t r, uint32_t off, V (&out)[S]) {
+  if constexpr (S == 1) {
+    out[0] = buf_load<V>(r, off);
+  } else {
+    static_assert(S == 2, "1 or 2 values per lane");
+    using V2 = V __attribute__((ext_vector_type(2)));
+    V2 w;
+    if constexpr (sizeof(V) == 2) {
+      w = __builtin_bit_cast(V2, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    } else if constexpr (sizeof(V) == 4) {
+      w = __builtin_bit_cast(V2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    } else {
+      static_assert(sizeof(V) == 8, "2, 4 or 8 bytes");
+      w = __builtin_bit_cast(V2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    }
+    out[0] = w.x;
+    out[1] = w.y;
+  }
+}
+
+// S consecutive values stored with one non-temporal store instruction
+template <typename V, int S>
+__device__ __forceinline__ void buf_store_nt_n(const V (&v)[S], __amdgpu_buffer_rsrc_t r,
+                                               uint32_t off) {
+  if constexpr (S == 1) {
+    buf_store_nt<V>(v[0], r, off);
+  } else {
+    static_assert(S == 2, "1 or 2 values per lane");
+    using V2 = V __attribute__((ext_vector_type(2)));
+    const V2 w = {v[0], v[1]};
+    if constexpr (sizeof(V) == 2) {
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, w), r, off, 0,
+                                            kNonTemporal);
+    } else if constexpr (sizeof(V) == 4) {
+      using U2 = unsigned int __attribute__((ext_vector_type(2)));
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, w), r, off, 0, kNonTemporal);
+    } else {
+      static_assert(sizeof(V) == 8, "2, 4 or 8 bytes");
+      using U4 = unsigned int __attribute__((ext_vector_type(4)));
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, w), r, off, 0, kNonTemporal);
+    }
+  }
+}
+
 template <int ST>
 struct Storage;
 // kNeq: the second-order planes hold the deviation a2 - u u (the

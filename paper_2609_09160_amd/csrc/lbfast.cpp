@@ -106,6 +106,7 @@ struct lbfast_ctx {
   bool scales_fixed = false;
   int tile_rows = 8;
   int z_chunk = 0;
+  int lane_sites = 1;
   bool two_phase = false;
   lbfast_phase_params pp;
   void* phi[2] = {nullptr, nullptr};  // phase field, two time levels
@@ -121,28 +122,46 @@ namespace {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// LDS of one step workgroup: staged populations x (rows + 2) x 66 columns
-size_t lds_bytes(int Q, int storage, int tile_rows) {
+// LDS of one step workgroup: staged populations x (rows + 2) x (64 S + 2)
+// columns, plus the x-halo column buffer
+size_t lds_bytes(int Q, int storage, int tile_rows, int lane_sites) {
   const size_t np = (Q == LBF_D3Q19) ? 16 : 24;
   const size_t c = (storage == LBF_F64) ? 8 : 4;
-  return c * np * static_cast<size_t>(tile_rows + 2) * 66;
+  return c * np * static_cast<size_t>(tile_rows + 2) * static_cast<size_t>(64 * lane_sites + 4);
 }
+constexpr size_t kLdsLimit = 160 * 1024;
 
-// default launch shape (measured on MI355X at 512^3): 8-row tiles for 32- and
-// 16-bit storage, 6-row tiles for FP64; z-chunks only when the column tiles
-// alone give fewer than ~512 workgroups (two per CU)
+// default launch shape (measured on MI355X at 512^3): two x-sites per lane
+// where nx allows it (even, at least one 128-wide tile), 8-row tiles (FP64:
+// 4 rows with two sites per lane, 6 with one) or the tallest that fits the
+// LDS; z-chunks only when the column tiles alone give too few workgroups
 void default_launch(lbfast_ctx* h) {
-  h->tile_rows = (h->p.storage == LBF_F64) ? 6 : 8;
+  // two sites per lane unless 128-wide tiles would leave more of the last
+  // tile empty than 64-wide ones
+  const int64_t waste1 = ceil_div(h->p.nx, 64) * 64 - h->p.nx;
+  const int64_t waste2 = ceil_div(h->p.nx, 128) * 128 - h->p.nx;
+  h->lane_sites = (h->p.nx % 2 == 0 && h->p.nx >= 128 && waste2 <= waste1) ? 2 : 1;
+  h->tile_rows = 4;
+  const bool f64 = h->p.storage == LBF_F64;
+  for (int ty : {f64 ? (h->lane_sites == 2 ? 4 : 6) : 8, 6, 4})
+    if (lds_bytes(h->p.lattice, h->p.storage, ty, h->lane_sites) <= kLdsLimit) {
+      h->tile_rows = ty;
+      break;
+    }
   h->z_chunk = 0;
 }
 
-int resolve_zchunk(const lbfast_ctx* h, int* tiles_x, int* tiles_y, int* zchunks, int* zchunk) {
-  *tiles_x = static_cast<int>(ceil_div(h->p.nx, 64));
-  *tiles_y = static_cast<int>(ceil_div(h->p.ny, h->tile_rows));
+int resolve_zchunk(const lbfast_ctx* h, int lane_sites, int tile_rows, int* tiles_x, int* tiles_y,
+                   int* zchunks, int* zchunk) {
+  *tiles_x = static_cast<int>(ceil_div(h->p.nx, 64 * lane_sites));
+  *tiles_y = static_cast<int>(ceil_div(h->p.ny, tile_rows));
   const int64_t cols = static_cast<int64_t>(*tiles_x) * *tiles_y;
   int64_t zc = h->z_chunk;
   if (zc <= 0) {
-    const int64_t want = ceil_div(512, cols);                  // chunks for ~512 blocks
+    // chunks for ~512 workgroups (~1024 for FP64 with two sites per lane,
+    // whose 4-row tiles are short)
+    const int64_t target = (h->p.storage == LBF_F64 && lane_sites == 2) ? 1024 : 512;
+    const int64_t want = ceil_div(target, cols);
     const int64_t maxc = h->p.nz >= 8 ? h->p.nz / 8 : 1;      // chunks of >= 8 planes
     const int64_t nchunks = want < 1 ? 1 : (want > maxc ? maxc : want);
     zc = ceil_div(h->p.nz, nchunks);
@@ -187,7 +206,10 @@ int step_args(const lbfast_ctx* h, lbf::StepArgs* a) {
   a->ny = static_cast<int>(h->p.ny);
   a->nz = static_cast<int>(h->p.nz);
   a->N = h->N;
-  if (int rc = resolve_zchunk(h, &a->tiles_x, &a->tiles_y, &a->zchunks, &a->zchunk)) return rc;
+  a->lane_sites = h->lane_sites;
+  if (int rc = resolve_zchunk(h, h->lane_sites, h->tile_rows, &a->tiles_x, &a->tiles_y,
+                              &a->zchunks, &a->zchunk))
+    return rc;
   a->omega = 1.0 / h->p.tau;
   for (int k = 0; k < 3; ++k) a->F[k] = h->Ffield ? 0.0 : h->p.force[k];
   for (int k = 0; k < 10; ++k) {
@@ -498,13 +520,38 @@ int lbfast_set_launch(lbfast_t h, int tile_rows, int z_chunk) {
     bool ok = false;
     for (int t : lbf::kTileRowsSupported) ok = ok || t == tile_rows;
     if (!ok) return fail(LBF_E_ARG, "tile_rows %d not supported (4, 6, 8 or 14)", tile_rows);
-    if (lds_bytes(h->p.lattice, h->p.storage, tile_rows) > 160 * 1024)
+    if (h->lane_sites == 2 && tile_rows > 8)
+      return fail(LBF_E_UNSUPPORTED, "two x-sites per lane support tiles of at most 8 rows");
+    const size_t lb = lds_bytes(h->p.lattice, h->p.storage, tile_rows, h->lane_sites);
+    if (lb > kLdsLimit)
       return fail(LBF_E_UNSUPPORTED, "tile_rows %d needs %zu bytes of LDS (limit 160 KiB)",
-                  tile_rows, lds_bytes(h->p.lattice, h->p.storage, tile_rows));
+                  tile_rows, lb);
   }
   if (z_chunk < 0) return fail(LBF_E_ARG, "z_chunk must be >= 0");
   if (tile_rows) h->tile_rows = tile_rows;
   if (z_chunk) h->z_chunk = z_chunk;
+  return LBF_OK;
+}
+
+int lbfast_set_lane_sites(lbfast_t h, int sites) {
+  g_err.clear();
+  if (int rc = check_handle(h)) return rc;
+  if (sites != 1 && sites != 2) return fail(LBF_E_ARG, "sites must be 1 or 2");
+  if (sites == 2 && h->p.nx % 2 != 0)
+    return fail(LBF_E_UNSUPPORTED, "two x-sites per lane need an even nx");
+  // keep the tile height if it fits, else the tallest one (of 8, 6, 4) that does
+  int ty = h->tile_rows;
+  if ((sites == 2 && ty > 8) || lds_bytes(h->p.lattice, h->p.storage, ty, sites) > kLdsLimit) {
+    ty = 0;
+    for (int t : {8, 6, 4})
+      if (lds_bytes(h->p.lattice, h->p.storage, t, sites) <= kLdsLimit) {
+        ty = t;
+        break;
+      }
+    if (ty == 0) return fail(LBF_E_UNSUPPORTED, "no tile height fits %d sites per lane", sites);
+  }
+  h->lane_sites = sites;
+  h->tile_rows = ty;
   return LBF_OK;
 }
 
@@ -724,6 +771,12 @@ int lbfast_adjoint(lbfast_t h, int64_t nsteps, int64_t every, const void* ckpt_d
   if (int rc = step_args(h, &fa)) return rc;
   aa = fa;
   aa.gF = gF_dev;
+  // The adjoint step reads 22 values per destination site: one site per lane
+  // (two would spill registers), 8-row tiles (FP64: 6)
+  aa.lane_sites = 1;
+  const int adj_rows = (h->p.storage == LBF_F64) ? 6 : 8;
+  if (int rc = resolve_zchunk(h, 1, adj_rows, &aa.tiles_x, &aa.tiles_y, &aa.zchunks, &aa.zchunk))
+    return rc;
   const int64_t nseg = (nsteps + every - 1) / every;
   const bool walls_y = h->p.bc[1] == LBF_WALLS;
   for (int64_t seg = nseg - 1; seg >= 0; --seg) {
@@ -742,7 +795,7 @@ int lbfast_adjoint(lbfast_t h, int64_t nsteps, int64_t every, const void* ckpt_d
       aa.dst = lam[cur ^ 1];
       aa.state_old = state(j);
       aa.state_new = state(j + 1);
-      e = lbf::launch_adjoint(h->p.lattice, h->p.storage, h->tile_rows, walls_y, aa, h->stream);
+      e = lbf::launch_adjoint(h->p.lattice, h->p.storage, adj_rows, walls_y, aa, h->stream);
       if (e != hipSuccess) return hip_fail(e, "adjoint launch");
       cur ^= 1;
     }

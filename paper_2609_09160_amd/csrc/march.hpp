@@ -17,20 +17,22 @@
 //                             only act as sources)
 //   P::Carry                  per-site data a source hands to its own
 //                             destination one plane later
-//   P::fetch<OWN>(a, pb, off, plane_bytes, raw)
+//   P::fetch<OWN, S>(a, pb, off, plane_bytes, raw[S])   S consecutive sites
 //   P::source<OWN>(a, raw, g[Q], carry)   g in units of 1/D (D = Lat<Q>::D)
-//   P::finish(a, sums, carry, pb, off, plane_bytes)   store one destination
+//   P::finish<S>(a, sums[S], carry[S], pb, off, plane_bytes)   store S
+//                             consecutive destinations
 //
 // gfx950 mapping (own design; the paper's 8x8x8 shared-memory tiles are prior
 // art for another GPU):
-//   * a workgroup owns a 64 x TY column tile of the x-y plane and a chunk of
-//     z-planes, and marches through z;
+//   * a workgroup owns a 64 S x TY column tile of the x-y plane (S = 1 or 2
+//     consecutive x-sites per lane, loaded and stored as one 1- or 2-wide
+//     access) and a chunk of z-planes, and marches through z;
 //   * wave w (0..TY+1) handles tile row w-1; waves 0 and TY+1 are the y-halo
 //     rows and also compute the two x-halo columns (lanes 0..TY+1);
-//   * per source plane, every thread evaluates its own site once and writes
-//     the values that leave its (x, y) column (16 for D3Q19, 24 for D3Q27) to
-//     LDS; after a barrier each interior thread pulls the 3x3 column
-//     neighbourhood from LDS;
+//   * per source plane, every thread evaluates its own sites once and writes
+//     the values that leave their (x, y) columns (16 for D3Q19, 24 for D3Q27)
+//     to LDS; after a barrier each interior thread pulls the 3x3 column
+//     neighbourhoods from LDS;
 //   * values travelling along z stay in registers: the ones with c_z=+1 wait
 //     one plane, the ones with c_z=-1 complete the previous plane, so each
 //     input is read from HBM once per update (plus L2-resident halos) and each
@@ -114,7 +116,7 @@ __device__ __forceinline__ void accumulate(Sums<C>& S, C v) {
   if constexpr (cy * cz == -1) S.pyz -= v;
 }
 
-template <class P, int TY, bool WALLY>
+template <class P, int TY, bool WALLY, int S>
 __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) {
   constexpr int Q = P::Q;
   using L = Lat<Q>;
@@ -124,8 +126,9 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
   using RawHalo = typename P::template Raw<false>;
   using Carry = typename P::Carry;
   constexpr int NP = L::NP;
-  constexpr int R = TY + 2;  // LDS rows: tile rows plus the two y-halo rows
-  constexpr int W = 66;      // LDS columns: 64 lanes plus the two x-halo columns
+  constexpr int R = TY + 2;       // LDS rows: tile rows plus the two y-halo rows
+  constexpr int TW = 64 * S;      // tile width: S consecutive x-sites per lane
+  constexpr int W = TW + 2;       // LDS columns: the tile plus the two x-halo columns
   __shared__ C lds[NP][R][W];
   __shared__ C colbuf[NP][2][R];  // next plane's x-halo columns (halo waves)
 
@@ -143,26 +146,27 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
   b /= a.tiles_y;
   const int txi = b % a.tiles_x;
   const int zci = b / a.tiles_x;
-  const int x0 = txi * 64, y0 = tyi * TY;
+  const int x0 = txi * TW, y0 = tyi * TY;
   const int z0 = zci * a.zchunk;
   const int z1 = min(z0 + a.zchunk, nz);
 
   // In-plane byte offsets are 32-bit (the host enforces nx*ny*8 < 2^32); the
   // per-plane base pointers are uniform, so every load and store is a scalar
-  // base plus one vector offset.
-  // own source site (every lane computes a valid, possibly wrapped, site)
-  const int xs = pmod(x0 + lane, nx);
+  // base plus one vector offset.  With S = 2 the host guarantees an even nx,
+  // so a lane's two sites never straddle the periodic wrap.
+  // own source sites (every lane computes valid, possibly wrapped, sites)
+  const int xs = pmod(x0 + S * lane, nx);
   const int ys = WALLY ? clampi(y0 + wv - 1, 0, ny - 1) : pmod(y0 + wv - 1, ny);
   const uint32_t off_s = (static_cast<uint32_t>(ys) * static_cast<uint32_t>(nx) + xs) * sizeof(T);
   // x-halo site: wave 0 takes the left column, wave R-1 the right one
   const bool do_halo = (wv == 0 || wv == R - 1) && lane < R;
   const int hcol = (wv == 0) ? 0 : W - 1;
-  const int xh = pmod(wv == 0 ? x0 - 1 : x0 + 64, nx);
+  const int xh = pmod(wv == 0 ? x0 - 1 : x0 + TW, nx);
   const int yh = WALLY ? clampi(y0 - 1 + lane, 0, ny - 1) : pmod(y0 - 1 + lane, ny);
   const uint32_t off_h = (static_cast<uint32_t>(yh) * static_cast<uint32_t>(nx) + xh) * sizeof(T);
-  // destination
+  // destinations
   const bool interior = (wv >= 1 && wv <= TY);
-  const int xd = x0 + lane, yd = y0 + wv - 1;
+  const int xd = x0 + S * lane, yd = y0 + wv - 1;
   const bool store_ok = interior && xd < nx && yd < ny;
   const uint32_t off_d = (static_cast<uint32_t>(yd) * static_cast<uint32_t>(nx) + xd) * sizeof(T);
   const bool wall_lo = WALLY && interior && yd == 0;
@@ -176,11 +180,14 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
     zs = zs >= nz ? zs - nz : zs;
     return zs >= nz ? zs % nz : zs;
   };
-  auto fetch_own = [&](const int zs, const uint32_t off, RawOwn& r) __attribute__((always_inline)) {
-    P::template fetch<true>(a, static_cast<int64_t>(zwrap(zs)) * plane, off, plane_bytes, r);
+  auto fetch_own = [&](const int zs, const uint32_t off, RawOwn (&r)[S]) __attribute__((always_inline)) {
+    P::template fetch<true, S>(a, static_cast<int64_t>(zwrap(zs)) * plane, off, plane_bytes, r);
   };
-  auto fetch_halo = [&](const int zs, const uint32_t off, RawHalo& r) __attribute__((always_inline)) {
-    P::template fetch<false>(a, static_cast<int64_t>(zwrap(zs)) * plane, off, plane_bytes, r);
+  auto fetch_row = [&](const int zs, const uint32_t off, RawHalo (&r)[S]) __attribute__((always_inline)) {
+    P::template fetch<false, S>(a, static_cast<int64_t>(zwrap(zs)) * plane, off, plane_bytes, r);
+  };
+  auto fetch_col = [&](const int zs, const uint32_t off, RawHalo (&r)[1]) __attribute__((always_inline)) {
+    P::template fetch<false, 1>(a, static_cast<int64_t>(zwrap(zs)) * plane, off, plane_bytes, r);
   };
   auto stage = [&](const C g[Q], const int row, const int col) __attribute__((always_inline)) {
     static_for<NP>([&](auto I) {
@@ -188,42 +195,57 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
       lds[i][row][col] = g[i];
     });
   };
-  // value i arriving at this thread's destination from the LDS plane; on a
-  // wall row the ones that would come from beyond the wall are dropped here
+  // value i arriving at the destination of own site s from the LDS plane; on
+  // a wall row the ones that would come from beyond the wall are dropped here
   // and replaced by the reflections added in body_interior
-  auto pulled = [&](auto I) __attribute__((always_inline)) -> C {
+  auto pulled = [&](auto I, const int s) __attribute__((always_inline)) -> C {
     constexpr int i = decltype(I)::value;
-    C v = lds[i][wv - L::cy(i)][lane + 1 - L::cx(i)];
+    C v = lds[i][wv - L::cy(i)][S * lane + s + 1 - L::cx(i)];
     if constexpr (WALLY && L::cy(i) == 1) v = wall_lo ? C(0) : v;
     if constexpr (WALLY && L::cy(i) == -1) v = wall_hi ? C(0) : v;
     return v;
   };
 
-  // Interior waves, one source plane zs per call.  acc: running sums of
+  // Interior waves, one source plane zs per call.  acc[s]: running sums of
   // destination plane zs-1 (all but its c_z=-1 values), completed and stored
-  // here; up: the c_z=+1 values that reach plane zs from zs-1; cd: the carry
-  // of the own site of plane zs-1.  rc holds this plane's inputs, rn receives
-  // the next plane's (one plane of latency hiding).
+  // here; up[s]: the c_z=+1 values that reach plane zs from zs-1; cd[s]: the
+  // carry of the own site of plane zs-1.  rc holds this plane's inputs, rn
+  // receives the next plane's (one plane of latency hiding).  The values along
+  // the three column directions (rest, c_z = +-1) never leave the thread and
+  // stay in registers (gc).
   constexpr int NU = (Q == 19) ? 5 : 9;  // directions with c_z = +1
-  auto body_interior = [&](const int zs, Sums<C>& acc, C (&up)[NU], Carry& cd, RawOwn& rc,
-                           RawOwn& rn, const int ahead) __attribute__((always_inline)) {
+  auto body_interior = [&](const int zs, Sums<C> (&acc)[S], C (&up)[S][NU], Carry (&cd)[S],
+                           RawOwn (&rc)[S], RawOwn (&rn)[S],
+                           const int ahead) __attribute__((always_inline)) {
     // unconditional (the last planes of a chunk fetch unused planes): a
     // conditional fetch makes the wait-count merge stall on the fresh loads
     fetch_own(zs + ahead, off_s, rn);
-    C g[Q];
-    Carry cs;
-    P::template source<true>(a, rc, g, cs);
-    stage(g, wv, lane + 1);
+    C gc[S][3];
+    Carry cs[S];
+    static_for<S>([&](auto SI) {
+      constexpr int s = decltype(SI)::value;
+      C g[Q];
+      P::template source<true>(a, rc[s], g, cs[s]);
+      stage(g, wv, S * lane + s + 1);
+      gc[s][0] = g[L::kRest];
+      gc[s][1] = g[L::kUp];
+      gc[s][2] = g[L::kDown];
+    });
     __syncthreads();
-    // c_z = -1 values complete destination plane zs-1
-    static_for<Q>([&](auto I) {
+    auto own = [&](auto I, const int s) __attribute__((always_inline)) -> C {
       constexpr int i = decltype(I)::value;
-      if constexpr (L::cz(i) == -1) {
-        if constexpr (i < NP)
-          accumulate<Q, i>(acc, pulled(I));
-        else
-          accumulate<Q, i>(acc, g[i]);
-      }
+      if constexpr (i < NP)
+        return pulled(I, s);
+      else
+        return gc[s][i - NP];
+    };
+    // c_z = -1 values complete destination plane zs-1
+    static_for<S>([&](auto SI) {
+      constexpr int s = decltype(SI)::value;
+      static_for<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (L::cz(i) == -1) accumulate<Q, i>(acc[s], own(I, s));
+      });
     });
     {
       // Every iteration issues the same stores (uniform memory-op counts keep
@@ -233,54 +255,49 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
       const bool live = zs - 1 >= z0 && zs - 1 < z1;
       const int64_t pb = static_cast<int64_t>(live ? zs - 1 : z0) * plane;
       const uint32_t off = (store_ok && live) ? off_d : plane_bytes;
-      P::finish(a, acc, cd, pb, off, plane_bytes);
+      P::template finish<S>(a, acc, cd, pb, off, plane_bytes);
     }
-    // destination plane zs: the c_z=+1 values from zs-1, then c_z = 0
-    zero(acc);
-    {
-      int u = 0;
+    static_for<S>([&](auto SI) {
+      constexpr int s = decltype(SI)::value;
+      // destination plane zs: the c_z=+1 values from zs-1, then c_z = 0
+      zero(acc[s]);
+      {
+        int u = 0;
+        static_for<Q>([&](auto I) {
+          constexpr int i = decltype(I)::value;
+          if constexpr (L::cz(i) == 1) accumulate<Q, i>(acc[s], up[s][u++]);
+        });
+      }
       static_for<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        if constexpr (L::cz(i) == 1) accumulate<Q, i>(acc, up[u++]);
+        if constexpr (L::cz(i) == 0) accumulate<Q, i>(acc[s], own(I, s));
       });
-    }
-    static_for<Q>([&](auto I) {
-      constexpr int i = decltype(I)::value;
-      if constexpr (L::cz(i) == 0) {
-        if constexpr (i < NP)
-          accumulate<Q, i>(acc, pulled(I));
-        else
-          accumulate<Q, i>(acc, g[i]);
+      if constexpr (WALLY) {
+        // halfway bounce-back: a value that would come from beyond the wall is
+        // the opposite one leaving x itself at the same time level (its own
+        // LDS slot: every direction with c_y != 0 is staged)
+        const int col = S * lane + s + 1;
+        if (wall_lo)
+          static_for<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if constexpr (L::cy(i) == 1) accumulate<Q, i>(acc[s], lds[L::opp(i)][wv][col]);
+          });
+        if (wall_hi)
+          static_for<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if constexpr (L::cy(i) == -1) accumulate<Q, i>(acc[s], lds[L::opp(i)][wv][col]);
+          });
+      }
+      cd[s] = cs[s];
+      // c_z = +1 values for destination plane zs+1
+      {
+        int u = 0;
+        static_for<Q>([&](auto I) {
+          constexpr int i = decltype(I)::value;
+          if constexpr (L::cz(i) == 1) up[s][u++] = own(I, s);
+        });
       }
     });
-    if constexpr (WALLY) {
-      // halfway bounce-back: a value that would come from beyond the wall is
-      // the opposite one leaving x itself at the same time level
-      if (wall_lo)
-        static_for<Q>([&](auto I) {
-          constexpr int i = decltype(I)::value;
-          if constexpr (L::cy(i) == 1) accumulate<Q, i>(acc, g[L::opp(i)]);
-        });
-      if (wall_hi)
-        static_for<Q>([&](auto I) {
-          constexpr int i = decltype(I)::value;
-          if constexpr (L::cy(i) == -1) accumulate<Q, i>(acc, g[L::opp(i)]);
-        });
-    }
-    cd = cs;
-    // c_z = +1 values for destination plane zs+1
-    {
-      int u = 0;
-      static_for<Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        if constexpr (L::cz(i) == 1) {
-          if constexpr (i < NP)
-            up[u++] = pulled(I);
-          else
-            up[u++] = g[i];
-        }
-      });
-    }
     __syncthreads();
   };
 
@@ -303,25 +320,26 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
         colbuf[i][hwave][lane] = g[i];
       });
   };
-  // rc: this plane's row site, rn: receives plane zs+ahead; hc: the column
+  // rc: this plane's row sites, rn: receives plane zs+ahead; hc: the column
   // site of plane zs+1, refilled after use with plane zs+1+U
-  auto body_halo = [&](const int zs, RawHalo& rc, RawHalo& rn, RawHalo& hc,
+  auto body_halo = [&](const int zs, RawHalo (&rc)[S], RawHalo (&rn)[S], RawHalo (&hc)[1],
                        const int ahead) __attribute__((always_inline)) {
-    fetch_halo(zs + ahead, off_s, rn);
+    fetch_row(zs + ahead, off_s, rn);
     if (do_halo)
       static_for<NP>([&](auto I) {
         constexpr int i = decltype(I)::value;
         lds[i][lane][hcol] = colbuf[i][hwave][lane];
       });
-    {
+    static_for<S>([&](auto SI) {
+      constexpr int s = decltype(SI)::value;
       C g[Q];
       Carry cs;
-      P::template source<false>(a, rc, g, cs);
-      stage(g, wv, lane + 1);
-    }
+      P::template source<false>(a, rc[s], g, cs);
+      stage(g, wv, S * lane + s + 1);
+    });
     __syncthreads();
-    col_to_buf(hc);
-    fetch_halo(zs + 1 + (ahead + 1), off_hf, hc);
+    col_to_buf(hc[0]);
+    fetch_col(zs + 1 + (ahead + 1), off_hf, hc);
     __syncthreads();
   };
 
@@ -336,14 +354,17 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
   const int trips = ((z1 - z0 + 2) + U - 1) / U;
   const bool interior_wave = __builtin_amdgcn_readfirstlane(static_cast<int>(interior)) != 0;
   if (interior_wave) {
-    Sums<C> acc;
-    zero(acc);
-    C up[NU];
-    Carry cd;
-    P::clear(cd);
+    Sums<C> acc[S];
+    C up[S][NU];
+    Carry cd[S];
 #pragma unroll
-    for (int u = 0; u < NU; ++u) up[u] = C(0);
-    RawOwn rr[U];
+    for (int s = 0; s < S; ++s) {
+      zero(acc[s]);
+      P::clear(cd[s]);
+#pragma unroll
+      for (int u = 0; u < NU; ++u) up[s][u] = C(0);
+    }
+    RawOwn rr[U][S];
     static_for<PF>([&](auto J) { fetch_own(z0 - 1 + J, off_s, rr[J]); });
 #pragma unroll 1
     for (int t = 0; t < trips; ++t) {
@@ -354,14 +375,14 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
       });
     }
   } else {
-    RawHalo rr[U], hh[U];
+    RawHalo rr[U][S], hh[U][1];
     {
-      RawHalo first;
-      fetch_halo(z0 - 1, off_hf, first);
-      col_to_buf(first);  // columns of the first source plane
+      RawHalo first[1];
+      fetch_col(z0 - 1, off_hf, first);
+      col_to_buf(first[0]);  // columns of the first source plane
     }
-    static_for<U>([&](auto J) { fetch_halo(z0 + J, off_hf, hh[J]); });
-    static_for<PF>([&](auto J) { fetch_halo(z0 - 1 + J, off_s, rr[J]); });
+    static_for<U>([&](auto J) { fetch_col(z0 + J, off_hf, hh[J]); });
+    static_for<PF>([&](auto J) { fetch_row(z0 - 1 + J, off_s, rr[J]); });
 #pragma unroll 1
     for (int t = 0; t < trips; ++t) {
       const int zb = z0 - 1 + t * U;
@@ -373,22 +394,36 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
   }
 }
 
-// LDS bytes of one workgroup: NP staged values x (TY+2) rows x 66 columns
-template <int Q, typename C, int TY>
+// LDS bytes of one workgroup: NP staged values x (TY+2) rows x (64 S + 2)
+// columns, plus the x-halo column buffer (NP x 2 x (TY+2))
+template <int Q, typename C, int TY, int S>
 constexpr size_t march_lds_bytes() {
-  return sizeof(C) * Lat<Q>::NP * (TY + 2) * 66;
+  return sizeof(C) * Lat<Q>::NP * (TY + 2) * (64 * S + 2 + 2);
 }
 constexpr size_t kLdsLimit = 160 * 1024;
 
-template <class P, int TY, bool WALLY>
-hipError_t launch_march(const StepArgs& a, hipStream_t stream) {
-  if constexpr (march_lds_bytes<P::Q, typename P::C, TY>() > kLdsLimit) {
+template <class P, int TY, bool WALLY, int S>
+hipError_t launch_march_s(const StepArgs& a, hipStream_t stream) {
+  if constexpr (march_lds_bytes<P::Q, typename P::C, TY, S>() > kLdsLimit) {
     return hipErrorInvalidConfiguration;
   } else {
     const int nb = a.tiles_x * a.tiles_y * a.zchunks;
-    hipLaunchKernelGGL((march_kernel<P, TY, WALLY>), dim3(nb), dim3(64 * (TY + 2)), 0, stream, a);
+    hipLaunchKernelGGL((march_kernel<P, TY, WALLY, S>), dim3(nb), dim3(64 * (TY + 2)), 0, stream,
+                       a);
     return hipGetLastError();
   }
+}
+
+// one or two consecutive x-sites per lane (a.lane_sites); the two-site form
+// exists for tiles of up to 8 rows (taller ones measured slower)
+template <class P, int TY, bool WALLY>
+hipError_t launch_march(const StepArgs& a, hipStream_t stream) {
+  if (a.lane_sites == 2) {
+    if constexpr (TY <= 8) return launch_march_s<P, TY, WALLY, 2>(a, stream);
+    return hipErrorInvalidValue;
+  }
+  if (a.lane_sites != 1) return hipErrorInvalidValue;
+  return launch_march_s<P, TY, WALLY, 1>(a, stream);
 }
 
 }  // namespace lbf

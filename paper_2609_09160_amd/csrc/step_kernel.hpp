@@ -100,24 +100,36 @@ struct Forward {
   // the force field has the compute type; its byte offset scales accordingly
   static constexpr uint32_t kFscale = sizeof(C) / sizeof(T);
 
-  template <bool OWN>
+  template <bool OWN, int NS>
   static __device__ __forceinline__ void fetch(const StepArgs& a, int64_t pb, uint32_t off,
-                                               uint32_t plane_bytes, Raw<OWN>& r) {
+                                               uint32_t plane_bytes, Raw<OWN> (&r)[NS]) {
     const T* __restrict__ src = static_cast<const T*>(a.src);
 #pragma unroll
-    for (int k = 0; k < 10; ++k)
-      r.m[k] = buf_load<T>(plane_rsrc(src + (k * a.N + pb), plane_bytes), off);
+    for (int k = 0; k < 10; ++k) {
+      T v[NS];
+      buf_load_n<T, NS>(plane_rsrc(src + (k * a.N + pb), plane_bytes), off, v);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) r[s].m[k] = v[s];
+    }
     if constexpr (FFIELD) {
       const C* __restrict__ Ff = static_cast<const C*>(a.Ffield);
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
-        r.F[k] = buf_load<C>(plane_rsrc(Ff + (k * a.N + pb), plane_bytes * kFscale), off * kFscale);
+      for (int k = 0; k < 3; ++k) {
+        C v[NS];
+        buf_load_n<C, NS>(plane_rsrc(Ff + (k * a.N + pb), plane_bytes * kFscale), off * kFscale, v);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) r[s].F[k] = v[s];
+      }
     }
     if constexpr (FNEXT && OWN) {
       const C* __restrict__ Fn = static_cast<const C*>(a.Fnext);
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
-        r.Fn[k] = buf_load<C>(plane_rsrc(Fn + (k * a.N + pb), plane_bytes * kFscale), off * kFscale);
+      for (int k = 0; k < 3; ++k) {
+        C v[NS];
+        buf_load_n<C, NS>(plane_rsrc(Fn + (k * a.N + pb), plane_bytes * kFscale), off * kFscale, v);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) r[s].Fn[k] = v[s];
+      }
     }
   }
 
@@ -144,24 +156,32 @@ struct Forward {
     source_pops<Q, C>(m, F[0], F[1], F[2], static_cast<C>(a.omega), g);
   }
 
-  static __device__ __forceinline__ void finish(const StepArgs& a, const Sums<C>& acc,
-                                                const Carry& c, int64_t pb, uint32_t off,
+  template <int NS>
+  static __device__ __forceinline__ void finish(const StepArgs& a, const Sums<C> (&acc)[NS],
+                                                const Carry (&c)[NS], int64_t pb, uint32_t off,
                                                 uint32_t plane_bytes) {
     T* __restrict__ dst = static_cast<T*>(a.dst);
-    C out[10];
-    finalize<Q, C>(acc, c.F[0], c.F[1], c.F[2], out);
-    if constexpr (S::kNeq) {
-      // store a2 - u u with the velocity as it will be read back
-      C ur[3];
+    C out[NS][10];
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
-        ur[k] = S::decode(S::encode(out[1 + k], a.inv_scale[1 + k]), a.scale[1 + k]);
+    for (int s = 0; s < NS; ++s) {
+      finalize<Q, C>(acc[s], c[s].F[0], c[s].F[1], c[s].F[2], out[s]);
+      if constexpr (S::kNeq) {
+        // store a2 - u u with the velocity as it will be read back
+        C ur[3];
 #pragma unroll
-      for (int k = 4; k < 10; ++k) out[k] -= ur[a2_a(k)] * ur[a2_b(k)];
+        for (int k = 0; k < 3; ++k)
+          ur[k] = S::decode(S::encode(out[s][1 + k], a.inv_scale[1 + k]), a.scale[1 + k]);
+#pragma unroll
+        for (int k = 4; k < 10; ++k) out[s][k] -= ur[a2_a(k)] * ur[a2_b(k)];
+      }
     }
 #pragma unroll
-    for (int k = 0; k < 10; ++k)
-      S::store_at(plane_rsrc(dst + (k * a.N + pb), plane_bytes), off, out[k], a.inv_scale[k]);
+    for (int k = 0; k < 10; ++k) {
+      T v[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) v[s] = S::encode(out[s][k], a.inv_scale[k]);
+      buf_store_nt_n<T, NS>(v, plane_rsrc(dst + (k * a.N + pb), plane_bytes), off);
+    }
   }
 };
 

@@ -98,7 +98,11 @@ class Solver:
         check(self.lib.lbfast_set_force_field(self.h, ctypes.c_void_p(F.data_ptr()), dt))
         self._force_field = F
 
-    def set_launch(self, tile_rows=0, z_chunk=0):
+    def set_launch(self, tile_rows=0, z_chunk=0, lane_sites=0):
+        """Launch shape: rows per tile, z-planes per workgroup, x-sites per
+        lane (0 keeps the current value).  Sites per lane are applied first."""
+        if lane_sites:
+            check(self.lib.lbfast_set_lane_sites(self.h, int(lane_sites)))
         check(self.lib.lbfast_set_launch(self.h, int(tile_rows), int(z_chunk)))
 
     def scales(self):

@@ -53,13 +53,15 @@ def _rel_max(got, want):
     return float(np.abs(got - want).max() / np.abs(want).max())
 
 
+@pytest.mark.parametrize("sites", [1, 2])
 @pytest.mark.parametrize("bc", [(0, 0, 0), (0, 1, 0)])
 @pytest.mark.parametrize("Q", [19, 27])
-def test_adjoint_matches_oracle_fp64(Q, bc):
-    """70 x 13 x 9 (two x tiles, ragged y and z tiles, small z-chunks),
-    random off-equilibrium state, per-site force std 1e-3, 40 steps in
-    segments of 7 (ragged last segment), linear objective J = r.m(T) with
-    random r: dJ/dF and dJ/dm0 element-wise against the FP64 CPU adjoint."""
+def test_adjoint_matches_oracle_fp64(Q, bc, sites):
+    """70 x 13 x 9 (ragged x, y and z tiles, small z-chunks; the recomputed
+    forward steps with one or two x-sites per lane), random off-equilibrium state,
+    per-site force std 1e-3, 40 steps in segments of 7 (ragged last segment),
+    linear objective J = r.m(T) with random r: dJ/dF and dJ/dm0 element-wise
+    against the FP64 CPU adjoint."""
     from oracle import adjoint as A
     shape = (70, 13, 9)
     N = int(np.prod(shape))
@@ -67,8 +69,9 @@ def test_adjoint_matches_oracle_fp64(Q, bc):
     F = inputs.random_force(shape, seed=32, std=1e-3).reshape(3, N)
     r = np.random.default_rng(33).standard_normal((10, N))
     tau, steps = 0.7, 40
-    say(f"adjoint fp64 vs oracle Q{Q} bc={bc}")
-    gF, g0, _ = gpu_adjoint(shape, tau, m0, F, steps, 7, r, lattice=Q, bc=bc, launch=(6, 3))
+    say(f"adjoint fp64 vs oracle Q{Q} bc={bc} sites={sites}")
+    gF, g0, _ = gpu_adjoint(shape, tau, m0, F, steps, 7, r, lattice=Q, bc=bc,
+                            launch=(4, 3, sites))
     wF, w0 = A.adjoint(Q, shape, tau, m0, F, steps, r, bc)
     eF, e0 = _rel_max(gF, wF), _rel_max(g0, w0)
     say(f"  dJ/dF {eF:.2e}, dJ/dm0 {e0:.2e}")

@@ -44,22 +44,26 @@ SHAPES = [(130, 19, 21), (7, 5, 3), (1, 1, 1), (65, 9, 40), (64, 16, 2)]
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("forcing", ["uniform", "field"])
 @pytest.mark.parametrize("walls", [False, True])
-def test_ragged_fp64(Q, shape, forcing, walls):
+@pytest.mark.parametrize("sites", [1, 2])
+def test_ragged_fp64(Q, shape, forcing, walls, sites):
     """Off-equilibrium random state, uniform or per-site force, periodic or
-    y-walls, ragged sizes and small z-chunks: 6 steps, FP64, <= 1e-12."""
+    y-walls, ragged sizes and small z-chunks, one or two x-sites per lane
+    (two: 128-wide tiles, also wider than the grid): 6 steps, FP64, <= 1e-12."""
     if walls and shape[1] < 2:
         pytest.skip("a walled axis needs >= 2 sites")
+    if sites == 2 and shape[0] % 2:
+        pytest.skip("two sites per lane need an even nx")
     tau = 0.7
     bc = (0, 1 if walls else 0, 0)
     m0 = inputs.random_state(shape, seed=sum(shape) + Q)
     F = inputs.random_force(shape, seed=7, std=1e-4)
     Fu = (2e-5, -1e-5, 3e-5)
-    say(f"ragged fp64 Q{Q} {shape} {forcing} walls={walls}")
+    say(f"ragged fp64 Q{Q} {shape} {forcing} walls={walls} sites={sites}")
     if forcing == "uniform":
-        got = gpu_run(shape, tau, m0, 6, lattice=Q, bc=bc, force=Fu, launch=(0, 4))
+        got = gpu_run(shape, tau, m0, 6, lattice=Q, bc=bc, force=Fu, launch=(0, 4, sites))
         want = oracle_run(shape, tau, m0, 6, lattice=Q, bc=bc, force=np.array(Fu))
     else:
-        got = gpu_run(shape, tau, m0, 6, lattice=Q, bc=bc, Ffield=F, launch=(0, 4))
+        got = gpu_run(shape, tau, m0, 6, lattice=Q, bc=bc, Ffield=F, launch=(0, 4, sites))
         want = oracle_run(shape, tau, m0, 6, lattice=Q, bc=bc, force=F)
     err = group_rel_err(got, want)
     say(f"  err {err:.3e}")
@@ -103,17 +107,18 @@ def test_channel_with_walls(storage, tol):
 
 @pytest.mark.parametrize("Q", [19, 27])
 def test_launch_shape_invariance(Q):
-    """Different tile heights and z-chunks agree to rounding (catches missing
-    barriers or halo mistakes that depend on the tiling; the heights are
-    separately compiled, so the last bits may differ), and one launch shape is
-    bitwise reproducible."""
+    """Different tile heights, z-chunks and x-sites per lane agree to rounding
+    (catches missing barriers or halo mistakes that depend on the tiling; the
+    shapes are separately compiled, so the last bits may differ), and one
+    launch shape is bitwise reproducible."""
     shape = (130, 37, 45)
     m0 = inputs.random_state(shape, seed=5)
-    ref = gpu_run(shape, 0.65, m0, 3, lattice=Q, storage="f32", launch=(8, 0))
-    again = gpu_run(shape, 0.65, m0, 3, lattice=Q, storage="f32", launch=(8, 0))
+    ref = gpu_run(shape, 0.65, m0, 3, lattice=Q, storage="f32", launch=(8, 0, 1))
+    again = gpu_run(shape, 0.65, m0, 3, lattice=Q, storage="f32", launch=(8, 0, 1))
     assert np.array_equal(again, ref)
     scale = np.abs(ref).max()
-    for launch in ((4, 0), (6, 0), (14, 0), (8, 3), (4, 7), (6, 45), (14, 5), (8, 1)):
+    for launch in ((4, 0, 1), (6, 0, 1), (14, 0, 1), (8, 3, 1), (4, 7, 2), (6, 45, 2),
+                   (8, 5, 2), (8, 1, 2), (4, 0, 2), (8, 0, 2)):
         got = gpu_run(shape, 0.65, m0, 3, lattice=Q, storage="f32", launch=launch)
         d = np.abs(got - ref).max()
         say(f"launch {launch}: max diff {d:.3e} (scale {scale:.3e})")

@@ -26,12 +26,14 @@ def _cuda():
 
 
 def gpu_two_phase(shape, tau, m0, phi0, steps, lattice=19, storage="f64", force=(0, 0, 0),
-                  scale=None, every=None):
+                  scale=None, every=None, sites=0):
     """Moments [10, nz, ny, nx] and phi [nz, ny, nx] (host float64) after
     `steps`; with `every`, also the per-plane max |v| sampled every `every`
     steps."""
     from paper_2609_09160_amd import Solver
     s = Solver(shape, tau, lattice=lattice, storage=storage, force=force, scale=scale)
+    if sites:
+        s.set_launch(4, 0, sites)
     s.enable_two_phase(SIGMA, W, DIFF)
     s.set_moments(np.ascontiguousarray(m0))
     s.set_phase(np.ascontiguousarray(phi0))
@@ -71,17 +73,19 @@ def _droplet_state(shape, R, seed, noise=True):
     return m, phi
 
 
+@pytest.mark.parametrize("sites", [1, 2])
 @pytest.mark.parametrize("Q", [19, 27])
-def test_two_phase_parity_fp64(Q):
+def test_two_phase_parity_fp64(Q, sites):
     """70 x 21 x 18 (ragged), off-centre droplet R = 6 with a perturbed flow
-    and a uniform body force, 30 steps, FP64: moments and phi element-wise."""
+    and a uniform body force, 30 steps, FP64, one or two x-sites per lane:
+    moments and phi element-wise."""
     shape = (70, 21, 18)
     m0, _ = _droplet_state(shape, 6, seed=Q)
     from oracle import two_phase as T
     phi0 = T.droplet(shape, 6, W, center=(30.3, 10.1, 8.7))
     Fb = (2e-6, -1e-6, 5e-7)
-    say(f"two-phase fp64 parity Q{Q}")
-    got, gphi, _ = gpu_two_phase(shape, 0.8, m0, phi0, 30, lattice=Q, force=Fb)
+    say(f"two-phase fp64 parity Q{Q} sites={sites}")
+    got, gphi, _ = gpu_two_phase(shape, 0.8, m0, phi0, 30, lattice=Q, force=Fb, sites=sites)
     want, wphi = oracle_two_phase(shape, 0.8, m0, phi0, 30, lattice=Q, force=np.array(Fb))
     em = group_rel_err(got, want)
     ep = float(np.abs(gphi - wphi).max() / np.abs(wphi).max())
