@@ -61,21 +61,56 @@ def make_input(shape, device):
     return inputs.solenoidal_field(shape, device=device)
 
 
-def time_steps(solver, steps, warmup):
+def energy_reader():
+    """Callable returning the GPU's accumulated energy in joules (amd-smi
+    energy counter of the device torch uses), or None where unavailable."""
+    try:
+        import amdsmi
+        import torch
+        amdsmi.amdsmi_init()
+        handles = amdsmi.amdsmi_get_processor_handles()
+        bus = getattr(torch.cuda.get_device_properties(0), "pci_bus_id", None)
+        pick = None
+        for h in handles:
+            bdf = amdsmi.amdsmi_get_gpu_device_bdf(h)
+            if bus is not None and int(bdf.split(":")[1], 16) == int(bus):
+                pick = h
+        if pick is None and len(handles) == 1:
+            pick = handles[0]
+        if pick is None:
+            return None
+
+        def read():
+            e = amdsmi.amdsmi_get_energy_count(pick)
+            return e["energy_accumulator"] * e["counter_resolution"] * 1e-6
+        read()
+        return read
+    except Exception:
+        return None
+
+
+def time_steps(solver, steps, warmup, energy=None):
+    """ms per step (= per launch); with `energy`, also joules over the timed
+    steps (None if unreadable)."""
     import torch
     solver.step(warmup)
     solver.sync()
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
+    e0 = energy() if energy else None
     start.record(solver.stream)
     solver.step(steps)
     end.record(solver.stream)
     torch.cuda.synchronize()
-    return start.elapsed_time(end) / steps  # ms per step (= per launch)
+    e1 = energy() if energy else None
+    ms = start.elapsed_time(end) / steps
+    if energy is None:
+        return ms
+    return ms, (e1 - e0 if e0 is not None and e1 is not None else None)
 
 
-def run_gpu(n, lattice, storage, steps, warmup, m0=None, launch=(0, 0)):
+def run_gpu(n, lattice, storage, steps, warmup, m0=None, launch=(0, 0), energy=None):
     import torch
     from paper_2609_09160_amd import Solver
     shape = (n, n, n)
@@ -88,7 +123,11 @@ def run_gpu(n, lattice, storage, steps, warmup, m0=None, launch=(0, 0)):
     s.set_moments(m0)
     if own:
         del m0
-    ms = time_steps(s, steps, warmup)
+    joules = None
+    if energy is not None:
+        ms, joules = time_steps(s, steps, warmup, energy)
+    else:
+        ms = time_steps(s, steps, warmup)
     red = s.reduce()
     s.close()
     del s
@@ -96,8 +135,12 @@ def run_gpu(n, lattice, storage, steps, warmup, m0=None, launch=(0, 0)):
     sites = n ** 3
     mlups = sites / (ms * 1e-3) / 1e6
     gbs = 20 * BYTES_PER_VALUE[storage] * sites / (ms * 1e-3) / 1e9
-    return {"mlups": mlups, "ms_per_step": ms, "algorithmic_GBs": gbs,
-            "hbm_frac": gbs / HBM_PEAK_GBS, "finite": bool(all(abs(v) < 1e300 for v in red))}
+    out = {"mlups": mlups, "ms_per_step": ms, "algorithmic_GBs": gbs,
+           "hbm_frac": gbs / HBM_PEAK_GBS, "finite": bool(all(abs(v) < 1e300 for v in red))}
+    if joules is not None:
+        out["nJ_per_lup"] = joules * 1e9 / (sites * steps)
+        out["avg_power_W"] = joules / (ms * 1e-3 * steps)
+    return out
 
 
 def stream_ceiling(n=512 ** 3, nplanes=10, reps=5):
@@ -287,7 +330,7 @@ def main():
     n = args.n
     sites = n ** 3
     main_run = run_gpu(n, args.lattice, args.storage, args.steps, args.warmup,
-                       launch=(args.tile_rows, args.z_chunk))
+                       launch=(args.tile_rows, args.z_chunk), energy=energy_reader())
     ms = main_run["ms_per_step"]
     value = main_run["mlups"]
     bpl = 20 * BYTES_PER_VALUE[args.storage]
@@ -319,6 +362,10 @@ def main():
                      "traffic": traffic,
                      "bytes_per_lup_algorithmic": bpl},
     }
+    if "nJ_per_lup" in main_run:
+        out["energy"] = {"nJ_per_lup": round(main_run["nJ_per_lup"], 4),
+                         "avg_power_W": round(main_run["avg_power_W"], 1),
+                         "source": "amd-smi energy counter over the timed steps"}
     gbs, _, _ = stream_ceiling()
     out["roofline"]["measured_stream_GBs"] = round(gbs, 1)
     out["roofline"]["frac_of_measured_stream"] = round(achieved / gbs, 4)

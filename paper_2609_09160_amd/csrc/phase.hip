@@ -16,8 +16,9 @@
 //
 // Two passes per step advance phi: the total flux V = phi u + lambda J (J the
 // normalised compression flux) at every site, stored with phi as one 4-wide
-// record, then phi' = phi - div(V) + D lap(phi).  One thread per site; the 26
-// neighbours are read through the caches.  Algorithmic traffic at FP32: flux
+// record, then phi' = phi - div(V) + D lap(phi) by a z-march with the records
+// staged in LDS.  The flux and force passes take one thread per site and read
+// their 26 neighbours through the caches.  Algorithmic traffic at FP32: flux
 // 32 B per lattice update (phi, u in; record out), update 20 B (record in;
 // phi out), force 16 B (phi in, F out), against the fused step's 104.
 #include "internal.hpp"
@@ -117,33 +118,68 @@ __global__ void __launch_bounds__(kPhaseThreads) flux_kernel(
   }
 }
 
-// phi' = phi - div(V) + D lap(phi)
+// phi' = phi - div(V) + D lap(phi).  A workgroup owns a 64 x kUpdRows column
+// tile and a chunk of z-planes and marches through z, keeping three planes
+// of records (with a one-site halo) in LDS: each record is read from memory
+// about once (plus halo) instead of 27 times.
+constexpr int kUpdRows = 8;
+
 template <typename C>
-__global__ void __launch_bounds__(kPhaseThreads) update_kernel(const Rec<C>* __restrict__ V,
+__global__ void __launch_bounds__(64 * kUpdRows) update_kernel(const Rec<C>* __restrict__ V,
                                                                C* __restrict__ out, int nx, int ny,
-                                                               int nz, int64_t N, C D) {
-  for (int64_t s = blockIdx.x * static_cast<int64_t>(kPhaseThreads) + threadIdx.x; s < N;
-       s += static_cast<int64_t>(gridDim.x) * kPhaseThreads) {
-    const Nbr n = neighbours(s, nx, ny, nz);
-    const C p0 = V[s].phi;
-    C dv = 0, l = 0;
+                                                               int nz, C D, int tiles_x,
+                                                               int tiles_y, int zchunk) {
+  constexpr int RY = kUpdRows + 2, RX = 66;
+  __shared__ Rec<C> t[3][RY][RX];
+  const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
+  int b = static_cast<int>(blockIdx.x);
+  const int tx = b % tiles_x;
+  b /= tiles_x;
+  const int ty = b % tiles_y;
+  const int zc = b / tiles_y;
+  const int x0 = tx * 64, y0 = ty * kUpdRows;
+  const int z0 = zc * zchunk, z1 = min(z0 + zchunk, nz);
+  const int64_t plane = static_cast<int64_t>(nx) * ny;
+  auto slot = [](int z) { return (z + 3) % 3; };  // z >= -1
+  auto load_plane = [&](int z) {
+    const int64_t zb = static_cast<int64_t>(wrap(z, nz)) * plane;
+    Rec<C>(*dst)[RX] = t[slot(z)];
+    for (int e = threadIdx.x; e < RY * RX; e += 64 * kUpdRows) {
+      const int ry = e / RX, rx = e - ry * RX;
+      const int xw = pmod(x0 + rx - 1, nx), yw = pmod(y0 + ry - 1, ny);
+      dst[ry][rx] = V[zb + static_cast<int64_t>(yw) * nx + xw];
+    }
+  };
+  const int x = x0 + lane, y = y0 + wy;
+  const bool mine = x < nx && y < ny;
+  load_plane(z0 - 1);
+  load_plane(z0);
+  for (int z = z0; z < z1; ++z) {
+    load_plane(z + 1);
+    __syncthreads();
+    if (mine) {
+      const C p0 = t[slot(z)][wy + 1][lane + 1].phi;
+      C dv = 0, l = 0;
 #pragma unroll
-    for (int dz = -1; dz <= 1; ++dz)
+      for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
-      for (int dy = -1; dy <= 1; ++dy)
+        for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-          if (dx == 0 && dy == 0 && dz == 0) continue;
-          const Rec<C> r = V[at(n, dx, dy, dz)];
-          const C k = C(k27(dx, dy, dz));
-          C cv = 0;
-          if (dx) cv += C(dx) * r.vx;
-          if (dy) cv += C(dy) * r.vy;
-          if (dz) cv += C(dz) * r.vz;
-          dv += k * cv;
-          l += k * (r.phi - p0);
-        }
-    out[s] = p0 - div_by<72>(dv) + D * div_by<36>(l);
+          for (int dx = -1; dx <= 1; ++dx) {
+            if (dx == 0 && dy == 0 && dz == 0) continue;
+            const Rec<C> r = t[slot(z + dz)][wy + 1 + dy][lane + 1 + dx];
+            const C k = C(k27(dx, dy, dz));
+            C cv = 0;
+            if (dx) cv += C(dx) * r.vx;
+            if (dy) cv += C(dy) * r.vy;
+            if (dz) cv += C(dz) * r.vz;
+            dv += k * cv;
+            l += k * (r.phi - p0);
+          }
+      out[static_cast<int64_t>(z) * plane + static_cast<int64_t>(y) * nx + x] =
+          p0 - div_by<72>(dv) + D * div_by<36>(l);
+    }
+    __syncthreads();
   }
 }
 
@@ -180,8 +216,17 @@ hipError_t phase_step_st(const PhaseArgs& a, hipStream_t s) {
                      static_cast<const T*>(a.state), static_cast<Rec<C>*>(a.J), a.nx, a.ny, a.nz,
                      a.N, static_cast<C>(a.lambda), static_cast<C>(a.eps), a.scale[1], a.scale[2],
                      a.scale[3]);
-  hipLaunchKernelGGL((update_kernel<C>), grid, block, 0, s, static_cast<const Rec<C>*>(a.J),
-                     static_cast<C*>(a.phi_out), a.nx, a.ny, a.nz, a.N, static_cast<C>(a.D));
+  // update: 64 x 8 column tiles, z-chunks of >= 8 planes for ~512 workgroups
+  const int tiles_x = (a.nx + 63) / 64, tiles_y = (a.ny + kUpdRows - 1) / kUpdRows;
+  const int cols = tiles_x * tiles_y;
+  int nch = (512 + cols - 1) / cols;
+  const int maxc = a.nz >= 8 ? a.nz / 8 : 1;
+  nch = nch < 1 ? 1 : (nch > maxc ? maxc : nch);
+  const int zchunk = (a.nz + nch - 1) / nch;
+  const int zchunks = (a.nz + zchunk - 1) / zchunk;
+  hipLaunchKernelGGL((update_kernel<C>), dim3(cols * zchunks), dim3(64 * kUpdRows), 0, s,
+                     static_cast<const Rec<C>*>(a.J), static_cast<C*>(a.phi_out), a.nx, a.ny,
+                     a.nz, static_cast<C>(a.D), tiles_x, tiles_y, zchunk);
   return hipGetLastError();
 }
 
