@@ -197,6 +197,34 @@ def test_argument_errors_on_device():
     s.close()
     big = _solver((8, 8, 8), storage="f64", lattice=27)
     with pytest.raises(LbfastError) as e:
-        big.set_launch(14, 0)  # 24 x 16 x 66 doubles of LDS exceed 160 KiB
+        big.set_launch(14, 0)  # 24 x 16 x 68 doubles of LDS exceed 160 KiB
     assert e.value.code == _lib.LBF_E_UNSUPPORTED
+    big.close()
+
+
+def test_lane_sites_selection():
+    """Two x-sites per lane need an even nx and tiles of at most 8 rows;
+    switching to them lowers a tile height whose LDS would not fit (FP64
+    D3Q27: 6-row tiles of 130 columns exceed 160 KiB, 4 rows fit)."""
+    from paper_2609_09160_amd import LbfastError, _lib
+    lib = _lib.load()
+    odd = _solver((65, 8, 8), storage="f32")
+    with pytest.raises(LbfastError) as e:
+        odd.set_launch(0, 0, 2)
+    assert e.value.code == _lib.LBF_E_UNSUPPORTED
+    assert lib.lbfast_set_lane_sites(odd.h, 3) == _lib.LBF_E_ARG
+    odd.close()
+    s = _solver((64, 8, 8), storage="f32")
+    s.set_launch(8, 0, 2)  # two sites per lane, 8-row tiles
+    with pytest.raises(LbfastError) as e:
+        s.set_launch(14, 0)  # not built with two sites per lane
+    assert e.value.code == _lib.LBF_E_UNSUPPORTED
+    s.close()
+    big = _solver((64, 8, 8), storage="f64", lattice=27)
+    big.set_launch(6, 0, 1)
+    big.set_launch(0, 0, 2)  # falls back to 4-row tiles
+    m = inputs.random_state((64, 8, 8), seed=2)
+    big.set_moments(m)
+    big.step(2)
+    assert np.isfinite(big.moments_host()).all()
     big.close()
