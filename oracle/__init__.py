@@ -46,14 +46,19 @@ def _load():
     lib.oracle_stream.argtypes = [ctypes.c_int, i64, i64, i64, ip, dp, dp]
     lib.oracle_run.argtypes = [ctypes.c_int, i64, i64, i64, ip, ctypes.c_double, dp, dp,
                                dp, i64]
-    lib.oracle_grad.argtypes = [i64, i64, i64, dp, dp]
-    lib.oracle_lap.argtypes = [i64, i64, i64, dp, dp]
+    lib.oracle_grad.argtypes = [i64, i64, i64, ip, dp, dp]
+    lib.oracle_lap.argtypes = [i64, i64, i64, ip, dp, dp]
     d = ctypes.c_double
-    lib.oracle_phase_step.argtypes = [i64, i64, i64, dp, dp, d, d, d, dp]
-    lib.oracle_capillary_force.argtypes = [i64, i64, i64, dp, d, d, dp, dp]
+    lib.oracle_phase_step.argtypes = [i64, i64, i64, ip, dp, dp, d, d, d, dp]
+    lib.oracle_capillary_force.argtypes = [i64, i64, i64, ip, dp, d, d, dp, dp]
+    lib.oracle_contrast_force.argtypes = [i64, i64, i64, ip, dp, dp, d, d, d, d, dp]
+    lib.oracle_collide_var.argtypes = [ctypes.c_int, i64, i64, i64, dp, dp, dp, dp, dp]
+    lib.oracle_moments_var.argtypes = [ctypes.c_int, i64, i64, i64, dp, dp, dp, dp]
+    lib.oracle_init_var.argtypes = [ctypes.c_int, i64, i64, i64, dp, dp, dp, dp]
     for f in ("oracle_init", "oracle_moments", "oracle_collide", "oracle_stream",
               "oracle_run", "oracle_grad", "oracle_lap", "oracle_phase_step",
-              "oracle_capillary_force"):
+              "oracle_capillary_force", "oracle_contrast_force", "oracle_collide_var",
+              "oracle_moments_var", "oracle_init_var"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib

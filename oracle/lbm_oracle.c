@@ -297,37 +297,63 @@ int oracle_run(int Q, int64_t nx, int64_t ny, int64_t nz, const int* bc, double 
 /* ------------------------------------------------------------------------
  * Two-component variant (section 2): phase field phi transported by the
  * conservative Allen-Cahn equation, Eq. (2), advanced by forward-time,
- * centred-space differences; capillary force F^s = mu grad(phi) with the
- * chemical potential mu = 4 beta phi (phi - 1)(phi - 1/2) - kappa lap(phi),
- * beta = 12 sigma / W, kappa = 3 sigma W / 2.  Spatial derivatives use the
- * D3Q27-weighted stencils of section 2:
+ * centred-space differences; density and viscosity blended linearly in phi,
+ * rho = rho_L + phi (rho_H - rho_L), nu = nu_L + phi (nu_H - nu_L); total
+ * force F = F^s + F^b + F^p + F^nu with
+ *   F^s = mu grad(phi),  mu = 4 beta phi (phi - 1)(phi - 1/2) - kappa lap(phi),
+ *         beta = 12 sigma / W, kappa = 3 sigma W / 2;
+ *   F^b = rho g (g: body acceleration);
+ *   F^p = - p* cs^2 grad(rho);
+ *   F^nu = - (nu omega / cs^2) (a2 - u u) . grad(rho)   (the printed form is
+ *         garbled; this is the viscous-stress term nu (grad u + grad u^T) .
+ *         grad(rho) with the stress written through the non-equilibrium
+ *         coefficient of Eq. (6)).
+ * Spatial derivatives use the D3Q27-weighted stencils of section 2:
  *   grad_a Psi(x) = (1/cs^2) sum_i w_i Psi(x + c_i) c_ia,
  *   lap Psi(x)    = (2/cs^2) sum_{i != 0} w_i [Psi(x + c_i) - Psi(x)]
  * (the printed Laplacian stencil is garbled; this is the second-order
- * Taylor-consistent form, zero on constants).  Periodic grid only.
+ * Taylor-consistent form, zero on constants).  Axes are periodic, or walled
+ * (bc[a] = 1): a neighbour beyond a wall is the mirror image of the site
+ * next to it, scalars and tangential vector components symmetric, the normal
+ * vector component antisymmetric (no flux through the wall).
  * ------------------------------------------------------------------------ */
 
-static int64_t wrap1(int64_t v, int64_t n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
-
-/* index of the periodic neighbour x + c (c in {-1, 0, 1}^3) */
-static int64_t site_shift(int64_t x, int64_t y, int64_t z, const int c[3], int64_t nx,
-                          int64_t ny, int64_t nz) {
-  return wrap1(x + c[0], nx) + nx * (wrap1(y + c[1], ny) + ny * wrap1(z + c[2], nz));
+/* index of the neighbour x + c (c in {-1, 0, 1}^3); *flip[a] = -1 where the
+ * step crossed a wall on axis a (the mirror site is returned) */
+static int64_t site_shift_bc(int64_t x, int64_t y, int64_t z, const int c[3], const int64_t n[3],
+                             const int* bc, int flip[3]) {
+  const int64_t X[3] = {x, y, z};
+  int64_t Y[3];
+  for (int a = 0; a < 3; ++a) {
+    int64_t v = X[a] + c[a];
+    flip[a] = 1;
+    if (v < 0 || v >= n[a]) {
+      if (bc && bc[a]) {
+        v = X[a];  /* halfway wall: the ghost beyond it mirrors the site next to it */
+        flip[a] = -1;
+      } else {
+        v = v < 0 ? v + n[a] : v - n[a];
+      }
+    }
+    Y[a] = v;
+  }
+  return Y[0] + n[0] * (Y[1] + n[1] * Y[2]);
 }
 
 /* out[a*N + s] = grad_a of the scalar field v at every site */
-int oracle_grad(int64_t nx, int64_t ny, int64_t nz, const double* v, double* out) {
+int oracle_grad(int64_t nx, int64_t ny, int64_t nz, const int* bc, const double* v, double* out) {
   lattice_t L;
   if (make_lattice(27, &L)) return -1;
-  const int64_t N = nx * ny * nz;
+  const int64_t N = nx * ny * nz, n[3] = {nx, ny, nz};
 #pragma omp parallel for schedule(static)
   for (int64_t z = 0; z < nz; ++z)
     for (int64_t y = 0; y < ny; ++y)
       for (int64_t x = 0; x < nx; ++x) {
         const int64_t s = x + nx * (y + ny * z);
         double g[3] = {0, 0, 0};
+        int flip[3];
         for (int i = 0; i < 27; ++i) {
-          const double vi = v[site_shift(x, y, z, L.c[i], nx, ny, nz)];
+          const double vi = v[site_shift_bc(x, y, z, L.c[i], n, bc, flip)];
           for (int a = 0; a < 3; ++a) g[a] += L.w[i] * vi * L.c[i][a];
         }
         for (int a = 0; a < 3; ++a) out[a * N + s] = g[a] / CS2;
@@ -336,18 +362,20 @@ int oracle_grad(int64_t nx, int64_t ny, int64_t nz, const double* v, double* out
 }
 
 /* out[s] = lap of v at every site */
-int oracle_lap(int64_t nx, int64_t ny, int64_t nz, const double* v, double* out) {
+int oracle_lap(int64_t nx, int64_t ny, int64_t nz, const int* bc, const double* v, double* out) {
   lattice_t L;
   if (make_lattice(27, &L)) return -1;
+  const int64_t n[3] = {nx, ny, nz};
 #pragma omp parallel for schedule(static)
   for (int64_t z = 0; z < nz; ++z)
     for (int64_t y = 0; y < ny; ++y)
       for (int64_t x = 0; x < nx; ++x) {
         const int64_t s = x + nx * (y + ny * z);
         double acc = 0.0;
+        int flip[3];
         for (int i = 0; i < 27; ++i) {
           if (L.c[i][0] == 0 && L.c[i][1] == 0 && L.c[i][2] == 0) continue;
-          acc += L.w[i] * (v[site_shift(x, y, z, L.c[i], nx, ny, nz)] - v[s]);
+          acc += L.w[i] * (v[site_shift_bc(x, y, z, L.c[i], n, bc, flip)] - v[s]);
         }
         out[s] = 2.0 * acc / CS2;
       }
@@ -355,19 +383,21 @@ int oracle_lap(int64_t nx, int64_t ny, int64_t nz, const double* v, double* out)
 }
 
 /* out[s] = div of the vector field V (3 planes) at every site */
-static int oracle_div(int64_t nx, int64_t ny, int64_t nz, const double* V, double* out) {
+static int oracle_div(int64_t nx, int64_t ny, int64_t nz, const int* bc, const double* V,
+                      double* out) {
   lattice_t L;
   if (make_lattice(27, &L)) return -1;
-  const int64_t N = nx * ny * nz;
+  const int64_t N = nx * ny * nz, n[3] = {nx, ny, nz};
 #pragma omp parallel for schedule(static)
   for (int64_t z = 0; z < nz; ++z)
     for (int64_t y = 0; y < ny; ++y)
       for (int64_t x = 0; x < nx; ++x) {
         const int64_t s = x + nx * (y + ny * z);
         double acc = 0.0;
+        int flip[3];
         for (int i = 0; i < 27; ++i) {
-          const int64_t si = site_shift(x, y, z, L.c[i], nx, ny, nz);
-          for (int a = 0; a < 3; ++a) acc += L.w[i] * L.c[i][a] * V[a * N + si];
+          const int64_t si = site_shift_bc(x, y, z, L.c[i], n, bc, flip);
+          for (int a = 0; a < 3; ++a) acc += L.w[i] * L.c[i][a] * flip[a] * V[a * N + si];
         }
         out[s] = acc / CS2;
       }
@@ -377,8 +407,8 @@ static int oracle_div(int64_t nx, int64_t ny, int64_t nz, const double* V, doubl
 /* One FTCS step of Eq. (2) in conservative form (unit time step):
  *   phi' = phi - div(phi u) + D lap(phi) - lambda div(phi (1 - phi) n),
  * lambda = 4 D / W, n = grad(phi) / (|grad(phi)| + eps).  u: 3 planes. */
-int oracle_phase_step(int64_t nx, int64_t ny, int64_t nz, const double* phi, const double* u,
-                      double D, double W, double eps, double* phi_new) {
+int oracle_phase_step(int64_t nx, int64_t ny, int64_t nz, const int* bc, const double* phi,
+                      const double* u, double D, double W, double eps, double* phi_new) {
   const int64_t N = nx * ny * nz;
   double* g = malloc(sizeof(double) * 3 * N);
   double* V = malloc(sizeof(double) * 3 * N);
@@ -388,7 +418,7 @@ int oracle_phase_step(int64_t nx, int64_t ny, int64_t nz, const double* phi, con
   double* t3 = malloc(sizeof(double) * N);
   int rc = (g && V && J && t1 && t2 && t3) ? 0 : -1;
   const double lambda = 4.0 * D / W;
-  if (!rc) rc = oracle_grad(nx, ny, nz, phi, g);
+  if (!rc) rc = oracle_grad(nx, ny, nz, bc, phi, g);
   if (!rc) {
 #pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < N; ++s) {
@@ -400,10 +430,10 @@ int oracle_phase_step(int64_t nx, int64_t ny, int64_t nz, const double* phi, con
         J[a * N + s] = c * g[a * N + s];
       }
     }
-    rc = oracle_div(nx, ny, nz, V, t1);
+    rc = oracle_div(nx, ny, nz, bc, V, t1);
   }
-  if (!rc) rc = oracle_lap(nx, ny, nz, phi, t2);
-  if (!rc) rc = oracle_div(nx, ny, nz, J, t3);
+  if (!rc) rc = oracle_lap(nx, ny, nz, bc, phi, t2);
+  if (!rc) rc = oracle_div(nx, ny, nz, bc, J, t3);
   if (!rc)
 #pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < N; ++s) phi_new[s] = phi[s] - t1[s] + D * t2[s] - lambda * t3[s];
@@ -412,15 +442,15 @@ int oracle_phase_step(int64_t nx, int64_t ny, int64_t nz, const double* phi, con
 }
 
 /* Capillary force F^s = mu grad(phi), plus a body force Fb (3 planes, or NULL). */
-int oracle_capillary_force(int64_t nx, int64_t ny, int64_t nz, const double* phi, double sigma,
-                           double W, const double* Fb, double* F) {
+int oracle_capillary_force(int64_t nx, int64_t ny, int64_t nz, const int* bc, const double* phi,
+                           double sigma, double W, const double* Fb, double* F) {
   const int64_t N = nx * ny * nz;
   double* g = malloc(sizeof(double) * 3 * N);
   double* l = malloc(sizeof(double) * N);
   int rc = (g && l) ? 0 : -1;
   const double beta = 12.0 * sigma / W, kappa = 1.5 * sigma * W;
-  if (!rc) rc = oracle_grad(nx, ny, nz, phi, g);
-  if (!rc) rc = oracle_lap(nx, ny, nz, phi, l);
+  if (!rc) rc = oracle_grad(nx, ny, nz, bc, phi, g);
+  if (!rc) rc = oracle_lap(nx, ny, nz, bc, phi, l);
   if (!rc)
 #pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < N; ++s) {
@@ -430,4 +460,92 @@ int oracle_capillary_force(int64_t nx, int64_t ny, int64_t nz, const double* phi
     }
   free(g); free(l);
   return rc;
+}
+
+/* Pressure and viscous force terms of the force split, added to F:
+ *   F += - p* cs^2 grad(rho) - (nu omega / cs^2) (a2 - u u) . grad(rho),
+ * with p*, u, a2 from the moments m (10 planes) and rho, nu, omega of phi. */
+int oracle_contrast_force(int64_t nx, int64_t ny, int64_t nz, const int* bc, const double* phi,
+                          const double* m, double rho_l, double rho_h, double nu_l, double nu_h,
+                          double* F) {
+  const int64_t N = nx * ny * nz;
+  double* g = malloc(sizeof(double) * 3 * N);
+  int rc = g ? 0 : -1;
+  if (!rc) rc = oracle_grad(nx, ny, nz, bc, phi, g);
+  if (!rc)
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < N; ++s) {
+      double ms[10], a2[3][3];
+      for (int k = 0; k < 10; ++k) ms[k] = m[k * N + s];
+      unpack_a2(ms, a2);
+      const double nu = nu_l + phi[s] * (nu_h - nu_l);
+      const double omega = 1.0 / (nu / CS2 + 0.5);
+      double grho[3];
+      for (int a = 0; a < 3; ++a) grho[a] = (rho_h - rho_l) * g[a * N + s];
+      for (int a = 0; a < 3; ++a) {
+        double visc = 0.0;
+        for (int b = 0; b < 3; ++b) visc += (a2[a][b] - ms[1 + a] * ms[1 + b]) * grho[b];
+        F[a * N + s] += -ms[0] * CS2 * grho[a] - nu * omega / CS2 * visc;
+      }
+    }
+  free(g);
+  return rc;
+}
+
+/* Steps 1-3 with a relaxation rate and a density per site (omega, rho: N
+ * values each): fpost = collide(moments(f)). */
+int oracle_collide_var(int Q, int64_t nx, int64_t ny, int64_t nz, const double* omega,
+                       const double* rho, const double* f, const double* F, double* fpost) {
+  lattice_t L;
+  if (make_lattice(Q, &L)) return -1;
+  const int64_t N = nx * ny * nz;
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < N; ++s) {
+    double fs[27], Fs[3], ms[10], fp[27];
+    for (int i = 0; i < Q; ++i) fs[i] = f[i * N + s];
+    site_force(F, N, s, Fs);
+    site_moments(&L, fs, Fs, rho[s], ms);
+    site_collide(&L, ms, Fs, rho[s], omega[s], fp);
+    for (int i = 0; i < Q; ++i) fpost[i * N + s] = fp[i];
+  }
+  return 0;
+}
+
+/* Reported moments with a density per site in the correction of Eq. (8). */
+int oracle_moments_var(int Q, int64_t nx, int64_t ny, int64_t nz, const double* rho,
+                       const double* f, const double* F, double* m) {
+  lattice_t L;
+  if (make_lattice(Q, &L)) return -1;
+  const int64_t N = nx * ny * nz;
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < N; ++s) {
+    double fs[27], Fs[3], ms[10];
+    for (int i = 0; i < Q; ++i) fs[i] = f[i * N + s];
+    site_force(F, N, s, Fs);
+    site_moments(&L, fs, Fs, rho[s], ms);
+    for (int k = 0; k < 10; ++k) m[k * N + s] = ms[k];
+  }
+  return 0;
+}
+
+/* Populations whose corrected moments (density per site) are exactly m. */
+int oracle_init_var(int Q, int64_t nx, int64_t ny, int64_t nz, const double* rho,
+                    const double* m, const double* F, double* f) {
+  lattice_t L;
+  if (make_lattice(Q, &L)) return -1;
+  const int64_t N = nx * ny * nz;
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < N; ++s) {
+    double Fs[3], ms[10];
+    site_force(F, N, s, Fs);
+    for (int k = 0; k < 10; ++k) ms[k] = m[k * N + s];
+    double u[3] = {ms[1], ms[2], ms[3]};
+    double a1[3], a2[3][3];
+    unpack_a2(ms, a2);
+    for (int a = 0; a < 3; ++a) a1[a] = u[a] - Fs[a] / (2.0 * rho[s]);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) a2[a][b] -= (Fs[a] * u[b] + Fs[b] * u[a]) / (2.0 * rho[s]);
+    for (int i = 0; i < Q; ++i) f[i * N + s] = hermite_series(&L, i, ms[0], a1, a2);
+  }
+  return 0;
 }
