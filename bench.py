@@ -249,11 +249,16 @@ def run_adjoint(n=192, steps=500, every=50, reps=2):
 TP_BYTES_PER_LUP = 172  # two-component step, FP32: fused step with F(t) and F(t+1) 104;
                         # phase flux 32 (phi, u in; flux and phi record out); phase
                         # update 20 (record in; phi out); capillary force 16 (phi in, F out)
+TP_CONTRAST_EXTRA = 48  # with density contrast: phi(t), phi(t+1) read by the fused step 8;
+                        # the force pass reads the 10 moments of the state 40
 
 
-def run_two_phase(n=256, steps=100, warmup=10, storage="f32"):
+def run_two_phase(n=256, steps=100, warmup=10, storage="f32", contrast=False):
     """Two-component workload: D3Q19 n^3 periodic, static droplet R = 40
-    centred, W = 4, sigma = 0.03, D = 0.1, equal densities, tau = 1."""
+    centred, W = 4, sigma = 0.03, D = 0.1, equal densities, tau = 1; with
+    `contrast`, densities 0.5 / 1.5 and relaxation times 0.65 / 1.7 (the
+    paper's layered-channel phases: per-site density and relaxation rate,
+    pressure and viscous force terms)."""
     import torch
     from paper_2609_09160_amd import Solver
     shape = (n, n, n)
@@ -263,8 +268,11 @@ def run_two_phase(n=256, steps=100, warmup=10, storage="f32"):
     phi = 0.5 * (1.0 - torch.tanh(2.0 * (r - 40.0) / 4.0))
     s = Solver(shape, 1.0, storage=storage,
                scale=None if storage in ("f32", "f64") else [2.0 ** -20] * 10)
-    s.enable_two_phase(0.03, 4.0, 0.1)
     s.set_moments(torch.zeros((10, n, n, n), dtype=torch.float64, device="cuda"))
+    if contrast:
+        s.enable_two_phase(0.03, 4.0, 0.1, rho=(0.5, 1.5), tau=(0.65, 1.7))
+    else:
+        s.enable_two_phase(0.03, 4.0, 0.1)
     s.set_phase(phi)
     del phi, r
     ms = time_steps(s, steps, warmup)
@@ -272,11 +280,13 @@ def run_two_phase(n=256, steps=100, warmup=10, storage="f32"):
     s.close()
     torch.cuda.empty_cache()
     sites = n ** 3
-    gbs = TP_BYTES_PER_LUP * sites / (ms * 1e-3) / 1e9
+    bpl = TP_BYTES_PER_LUP + (TP_CONTRAST_EXTRA if contrast else 0)
+    gbs = bpl * sites / (ms * 1e-3) / 1e9
     return {"mlups": round(sites / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
             "workload": f"D3Q19 {storage.upper()} {n}^3 periodic, static droplet R=40 W=4 "
-                        "sigma=0.03 D=0.1, equal densities, tau=1",
-            "bytes_per_lup_algorithmic": TP_BYTES_PER_LUP,
+                        "sigma=0.03 D=0.1, " + ("densities 0.5/1.5, tau 0.65/1.7" if contrast
+                                                else "equal densities, tau=1"),
+            "bytes_per_lup_algorithmic": bpl,
             "algorithmic_GBs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
@@ -399,6 +409,7 @@ def main():
         out["adjoint"] = run_adjoint()
     if not args.no_variants:
         out["two_phase"] = run_two_phase()
+        out["two_phase_contrast"] = run_two_phase(contrast=True)
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         out["cpu_baseline"] = cpu_baseline(args.lattice)
     print(json.dumps(out), flush=True)

@@ -160,24 +160,30 @@ int lbfast_set_lane_sites(lbfast_t h, int sites);
 /* Two-component variant (section 2): a phase field phi in [0, 1] (1: heavy
  * phase) transported by the conservative Allen-Cahn equation, Eq. (2),
  * advanced by forward-time centred-space differences with the D3Q27-weighted
- * derivative stencils of section 2, and the capillary force
- * F = mu grad(phi), mu = 4 beta phi (phi - 1)(phi - 1/2) - kappa lap(phi),
- * beta = 12 sigma / W, kappa = 3 sigma W / 2, plus the uniform params.force.
- * This build supports equal phase densities (rho_l = rho_h = 1) and
- * viscosities (tau_l = tau_h = params.tau), where the pressure and viscous
- * force terms vanish; other values give LBF_E_UNSUPPORTED.  Periodic grids
- * only; no per-site force field.  Each lbfast_step then performs, in order:
- * phi(t+1) from phi(t) and u(t); F(t+1) from phi(t+1); the fused step with
- * F(t) at the sources and F(t+1) in the correction of Eq. (8).  FTCS is
- * stable for diffusivity < ~0.34 with these stencils (not checked). */
+ * derivative stencils of section 2.  Density and viscosity are blended
+ * linearly in phi, rho = rho_l + phi (rho_h - rho_l), nu = nu_l + phi
+ * (nu_h - nu_l), nu_k = (tau_k - 1/2)/3, so the relaxation rate is per site
+ * (params.tau is not used in this mode).  The force is
+ *   F = mu grad(phi) + rho g - p* cs^2 grad(rho)
+ *       - (nu omega / cs^2)(a2 - u u) . grad(rho),
+ * mu = 4 beta phi (phi - 1)(phi - 1/2) - kappa lap(phi), beta = 12 sigma/W,
+ * kappa = 3 sigma W / 2, g = params.force read as a body acceleration (the
+ * same as a force per unit volume where rho = 1); the last two terms vanish
+ * at equal densities.  Walls: y only, with mirror images for the phase-field
+ * stencils.  No per-site force field in this mode.  Each lbfast_step then
+ * performs, in order: phi(t+1) from phi(t) and u(t); F(t+1) from phi(t+1)
+ * (its pressure and viscous terms from p*, u, a2 at t); the fused step with
+ * F(t)/rho(t) and omega(t) at the sources and F(t+1)/rho(t+1) in the
+ * correction of Eq. (8).  FTCS is stable for diffusivity < ~0.34 with these
+ * stencils (not checked). */
 typedef struct lbfast_phase_params {
   uint32_t struct_size; /* = sizeof(lbfast_phase_params) */
   int32_t reserved0;    /* must be zero */
   double sigma;         /* surface tension, >= 0 */
   double width;         /* interface thickness W, > 0 */
   double diffusivity;   /* D of Eq. (2), >= 0; lambda = 4 D / W */
-  double rho_l, rho_h;  /* phase densities: both 1 */
-  double tau_l, tau_h;  /* phase relaxation times: both params.tau */
+  double rho_l, rho_h;  /* phase densities (light, heavy), > 0 */
+  double tau_l, tau_h;  /* phase relaxation times, > 1/2 */
 } lbfast_phase_params;
 
 /* Switch the handle to the two-component variant.  The library allocates
@@ -185,7 +191,8 @@ typedef struct lbfast_phase_params {
  * time levels, and the phase flux.  phi starts at 0. */
 int lbfast_enable_two_phase(lbfast_t h, const lbfast_phase_params* pp);
 /* Copy the phase field (N values, dtype LBF_F64 or LBF_F32, host or device)
- * in or out.  set also computes the force of the current time level. */
+ * in or out.  set also computes the force of the current time level, from
+ * phi and (density contrast) the current moments: set the moments first. */
 int lbfast_set_phase(lbfast_t h, const void* phi, int dtype, int on_device);
 int lbfast_get_phase(lbfast_t h, void* phi, int dtype, int on_device);
 

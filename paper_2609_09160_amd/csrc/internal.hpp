@@ -14,6 +14,12 @@ struct StepArgs {
   const void* Ffield;  // 3 planes of the compute type, or nullptr (uniform F)
   const void* Fnext;   // force of the next time level for the correction, or
                        // nullptr (static force: Ffield serves both)
+  // two-component flow with density and viscosity contrast (else nullptr):
+  // phase field at t (sources) and t+1 (destinations), N values of the
+  // compute type; rho = rho_l + phi (rho_h - rho_l), likewise nu
+  const void* phi_src;
+  const void* phi_dst;
+  double rho_l, rho_h, nu_l, nu_h;
   int nx, ny, nz;
   int64_t N;           // plane stride = nx*ny*nz
   int tiles_x, tiles_y, zchunks, zchunk;
@@ -51,8 +57,11 @@ struct PhaseArgs {
   int nx, ny, nz;
   int64_t N;
   double D, lambda, beta, kappa, eps;
-  double Fb[3];       // uniform body force added to the capillary force
+  double Fb[3];       // body acceleration g: the force adds rho(phi) g
   float scale[10];    // storage scales (16-bit storage)
+  int walls_y;        // halfway walls in y: mirror images for the stencils
+  int contrast;       // add the pressure and viscous force terms
+  double rho_l, rho_h, nu_l, nu_h;
 };
 // phi_out = FTCS step of the Allen-Cahn equation from phi and the state's u
 hipError_t launch_phase_step(int storage, const PhaseArgs& a, hipStream_t stream);

@@ -217,6 +217,14 @@ int step_args(const lbfast_ctx* h, lbf::StepArgs* a) {
     a->inv_scale[k] = h->inv_scale[k];
   }
   a->Ffield = h->Ffield;
+  if (h->two_phase) {
+    // the phases' relaxation times replace params.tau
+    a->omega = 1.0 / h->pp.tau_l;
+    a->rho_l = h->pp.rho_l;
+    a->rho_h = h->pp.rho_h;
+    a->nu_l = (h->pp.tau_l - 0.5) / 3.0;
+    a->nu_h = (h->pp.tau_h - 0.5) / 3.0;
+  }
   return LBF_OK;
 }
 
@@ -246,9 +254,21 @@ lbf::PhaseArgs phase_args(const lbfast_ctx* h) {
   a.beta = 12.0 * h->pp.sigma / h->pp.width;
   a.kappa = 1.5 * h->pp.sigma * h->pp.width;
   a.eps = 1e-12;  // n = grad(phi) / (|grad(phi)| + eps)
-  for (int k = 0; k < 3; ++k) a.Fb[k] = h->p.force[k];
+  for (int k = 0; k < 3; ++k) a.Fb[k] = h->p.force[k];  // body acceleration
   for (int k = 0; k < 10; ++k) a.scale[k] = h->scale[k];
+  a.walls_y = h->p.bc[1] == LBF_WALLS;
+  a.contrast = h->pp.rho_l != h->pp.rho_h;
+  a.rho_l = h->pp.rho_l;
+  a.rho_h = h->pp.rho_h;
+  a.nu_l = (h->pp.tau_l - 0.5) / 3.0;
+  a.nu_h = (h->pp.tau_h - 0.5) / 3.0;
   return a;
+}
+
+// phases of unequal density or viscosity, or a density other than 1: the
+// step reads the phase field for a density and relaxation rate per site
+bool variable_properties(const lbfast_ctx* h) {
+  return h->pp.rho_l != 1.0 || h->pp.rho_h != 1.0 || h->pp.tau_l != h->pp.tau_h;
 }
 
 int check_adjoint_args(const lbfast_ctx* h, int64_t nsteps, int64_t every) {
@@ -575,6 +595,10 @@ int lbfast_step(lbfast_t h, int64_t n) {
       if (e != hipSuccess) return hip_fail(e, "phase-field launch");
       a.Ffield = h->Fph[h->pcur];
       a.Fnext = h->Fph[h->pcur ^ 1];
+      if (variable_properties(h)) {
+        a.phi_src = h->phi[h->pcur];
+        a.phi_dst = h->phi[h->pcur ^ 1];
+      }
     }
     if (int rc = launch_forward(h, a)) return rc;
     h->cur ^= 1;
@@ -595,13 +619,14 @@ int lbfast_enable_two_phase(lbfast_t h, const lbfast_phase_params* pp) {
   if (!std::isfinite(pp->width) || !(pp->width > 0)) return fail(LBF_E_ARG, "width must be > 0");
   if (!std::isfinite(pp->diffusivity) || pp->diffusivity < 0)
     return fail(LBF_E_ARG, "diffusivity must be >= 0");
-  if (pp->rho_l != 1.0 || pp->rho_h != 1.0)
-    return fail(LBF_E_UNSUPPORTED, "density contrast is not built: rho_l = rho_h = 1 required");
-  if (pp->tau_l != h->p.tau || pp->tau_h != h->p.tau)
-    return fail(LBF_E_UNSUPPORTED, "viscosity contrast is not built: tau_l = tau_h = tau required");
-  for (int ax = 0; ax < 3; ++ax)
-    if (h->p.bc[ax] != LBF_PERIODIC)
-      return fail(LBF_E_UNSUPPORTED, "the two-component variant needs a periodic grid");
+  if (!std::isfinite(pp->rho_l) || !std::isfinite(pp->rho_h) || !(pp->rho_l > 0) ||
+      !(pp->rho_h > 0))
+    return fail(LBF_E_ARG, "phase densities must be finite and > 0");
+  if (!std::isfinite(pp->tau_l) || !std::isfinite(pp->tau_h) || !(pp->tau_l > 0.5) ||
+      !(pp->tau_h > 0.5))
+    return fail(LBF_E_ARG, "phase relaxation times must be finite and > 1/2");
+  if (h->p.bc[0] != LBF_PERIODIC || h->p.bc[2] != LBF_PERIODIC)
+    return fail(LBF_E_UNSUPPORTED, "walls are supported on the y axis only");
   if (h->Ffield) return fail(LBF_E_STATE, "a per-site force field is set");
   if (h->two_phase) return fail(LBF_E_STATE, "two-component variant already enabled");
   DeviceGuard g(h->device);

@@ -2,9 +2,13 @@
 // 2): the conservative Allen-Cahn equation, Eq. (2), advanced by
 // forward-time centred-space differences, and the capillary force
 // F^s = mu grad(phi), mu = 4 beta phi (phi - 1)(phi - 1/2) - kappa lap(phi),
-// beta = 12 sigma / W, kappa = 3 sigma W / 2.  With equal phase densities
-// and viscosities the pressure and viscous force terms vanish, so the total
-// force is F^s plus the uniform body force.
+// beta = 12 sigma / W, kappa = 3 sigma W / 2, plus rho(phi) g for a body
+// acceleration g and, with density contrast, the pressure and viscous terms
+// of the force split (rho, nu blended linearly in phi; the printed viscous
+// term is garbled, this is -(nu omega / cs^2)(a2 - u u).grad(rho), the
+// viscous stress written through the non-equilibrium coefficient of
+// Eq. (6)).  Halfway walls in y take mirror images for the stencils, the
+// flux normal to the wall reversed.
 //
 // Derivatives use the D3Q27-weighted stencils of section 2 (weights
 // k_i / 216 with k = 64, 16, 4, 1 for |c|^2 = 0..3):
@@ -35,13 +39,15 @@ __device__ constexpr int k27(int dx, int dy, int dz) {
   return c2 == 0 ? 64 : (c2 == 1 ? 16 : (c2 == 2 ? 4 : 1));
 }
 
-// periodic neighbour offsets of site (x, y, z): ox[d+1] etc.
+// neighbour offsets of site (x, y, z): ox[d+1] etc.; periodic, or with
+// halfway walls in y (walls_y) where the site beyond a wall is the mirror
+// image of the one next to it
 struct Nbr {
   int64_t ox[3], oy[3], oz[3];
   int64_t s;
 };
 
-__device__ __forceinline__ Nbr neighbours(int64_t s, int nx, int ny, int nz) {
+__device__ __forceinline__ Nbr neighbours(int64_t s, int nx, int ny, int nz, bool walls_y) {
   Nbr n;
   const int64_t plane = static_cast<int64_t>(nx) * ny;
   const int z = static_cast<int>(s / plane);
@@ -50,7 +56,7 @@ __device__ __forceinline__ Nbr neighbours(int64_t s, int nx, int ny, int nz) {
   const int x = static_cast<int>(r - static_cast<int64_t>(y) * nx);
   for (int d = -1; d <= 1; ++d) {
     n.ox[d + 1] = wrap(x + d, nx);
-    n.oy[d + 1] = static_cast<int64_t>(wrap(y + d, ny)) * nx;
+    n.oy[d + 1] = static_cast<int64_t>(walls_y ? clampi(y + d, 0, ny - 1) : wrap(y + d, ny)) * nx;
     n.oz[d + 1] = static_cast<int64_t>(wrap(z + d, nz)) * plane;
   }
   n.s = s;
@@ -99,12 +105,13 @@ template <int ST>
 __global__ void __launch_bounds__(kPhaseThreads) flux_kernel(
     const typename Storage<ST>::C* __restrict__ phi, const typename Storage<ST>::T* __restrict__ st,
     Rec<typename Storage<ST>::C>* __restrict__ V, int nx, int ny, int nz, int64_t N,
-    typename Storage<ST>::C lambda, typename Storage<ST>::C eps, float s1, float s2, float s3) {
+    typename Storage<ST>::C lambda, typename Storage<ST>::C eps, float s1, float s2, float s3,
+    bool walls_y) {
   using S = Storage<ST>;
   using C = typename S::C;
   for (int64_t s = blockIdx.x * static_cast<int64_t>(kPhaseThreads) + threadIdx.x; s < N;
        s += static_cast<int64_t>(gridDim.x) * kPhaseThreads) {
-    const Nbr n = neighbours(s, nx, ny, nz);
+    const Nbr n = neighbours(s, nx, ny, nz, walls_y);
     C g[3], l;
     grad_lap(phi, n, g, l);
     const C p = phi[s];
@@ -128,7 +135,8 @@ template <typename C>
 __global__ void __launch_bounds__(64 * kUpdRows) update_kernel(const Rec<C>* __restrict__ V,
                                                                C* __restrict__ out, int nx, int ny,
                                                                int nz, C D, int tiles_x,
-                                                               int tiles_y, int zchunk) {
+                                                               int tiles_y, int zchunk,
+                                                               bool walls_y) {
   constexpr int RY = kUpdRows + 2, RX = 66;
   __shared__ Rec<C> t[3][RY][RX];
   const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
@@ -146,8 +154,13 @@ __global__ void __launch_bounds__(64 * kUpdRows) update_kernel(const Rec<C>* __r
     Rec<C>(*dst)[RX] = t[slot(z)];
     for (int e = threadIdx.x; e < RY * RX; e += 64 * kUpdRows) {
       const int ry = e / RX, rx = e - ry * RX;
-      const int xw = pmod(x0 + rx - 1, nx), yw = pmod(y0 + ry - 1, ny);
-      dst[ry][rx] = V[zb + static_cast<int64_t>(yw) * nx + xw];
+      const int xw = pmod(x0 + rx - 1, nx), yr = y0 + ry - 1;
+      // beyond a y wall: the mirror image, its flux normal to the wall reversed
+      const bool ghost = walls_y && (yr < 0 || yr >= ny);
+      const int yw = walls_y ? clampi(yr, 0, ny - 1) : pmod(yr, ny);
+      Rec<C> v = V[zb + static_cast<int64_t>(yw) * nx + xw];
+      if (ghost) v.vy = -v.vy;
+      dst[ry][rx] = v;
     }
   };
   const int x = x0 + lane, y = y0 + wy;
@@ -183,22 +196,51 @@ __global__ void __launch_bounds__(64 * kUpdRows) update_kernel(const Rec<C>* __r
   }
 }
 
-// F = mu grad(phi) + Fb
-template <typename C>
-__global__ void __launch_bounds__(kPhaseThreads) force_kernel(const C* __restrict__ phi,
-                                                              C* __restrict__ F, int nx, int ny,
-                                                              int nz, int64_t N, C beta, C kappa,
-                                                              C Fbx, C Fby, C Fbz) {
+// F = mu grad(phi) + rho(phi) g, plus (contrast) the pressure and viscous
+// terms - p* cs^2 grad(rho) - (nu omega / cs^2) (a2 - u u) . grad(rho), with
+// p*, u, a2 of the state at the previous time level
+template <int ST, bool CONTRAST>
+__global__ void __launch_bounds__(kPhaseThreads) force_kernel(
+    const typename Storage<ST>::C* __restrict__ phi, const typename Storage<ST>::T* __restrict__ st,
+    typename Storage<ST>::C* __restrict__ F, int nx, int ny, int nz, int64_t N, PhaseArgs pa) {
+  using S = Storage<ST>;
+  using C = typename S::C;
+  const C beta = static_cast<C>(pa.beta), kappa = static_cast<C>(pa.kappa);
+  const C rl = static_cast<C>(pa.rho_l), dr = static_cast<C>(pa.rho_h - pa.rho_l);
+  const C nl = static_cast<C>(pa.nu_l), dn = static_cast<C>(pa.nu_h - pa.nu_l);
   for (int64_t s = blockIdx.x * static_cast<int64_t>(kPhaseThreads) + threadIdx.x; s < N;
        s += static_cast<int64_t>(gridDim.x) * kPhaseThreads) {
-    const Nbr n = neighbours(s, nx, ny, nz);
+    const Nbr n = neighbours(s, nx, ny, nz, pa.walls_y != 0);
     C g[3], l;
     grad_lap(phi, n, g, l);
     const C p = phi[s];
     const C mu = C(4) * beta * p * (p - C(1)) * (p - C(0.5)) - kappa * l;
-    F[s] = mu * g[0] + Fbx;
-    F[N + s] = mu * g[1] + Fby;
-    F[2 * N + s] = mu * g[2] + Fbz;
+    const C rho = rl + p * dr;
+    C f[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f[k] = mu * g[k] + rho * static_cast<C>(pa.Fb[k]);
+    if constexpr (CONTRAST) {
+      C m[10];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) m[k] = S::load(st + k * N, s, pa.scale[k]);
+      // the non-equilibrium part a2 - u u (16-bit storage keeps it directly)
+      if constexpr (!S::kNeq) {
+#pragma unroll
+        for (int k = 4; k < 10; ++k) m[k] -= m[1 + a2_a(k)] * m[1 + a2_b(k)];
+      }
+      const C nu = nl + p * dn;
+      const C omega = C(1) / (C(3) * nu + C(0.5));
+      const C gr[3] = {dr * g[0], dr * g[1], dr * g[2]};
+      const C cv = C(3) * nu * omega;  // nu omega / cs^2
+      const C cp = m[0] * C(1.0 / 3.0);
+      // (a2 - u u) . grad(rho), rows xx xy xz / xy yy yz / xz yz zz
+      f[0] += -cp * gr[0] - cv * (m[4] * gr[0] + m[7] * gr[1] + m[8] * gr[2]);
+      f[1] += -cp * gr[1] - cv * (m[7] * gr[0] + m[5] * gr[1] + m[9] * gr[2]);
+      f[2] += -cp * gr[2] - cv * (m[8] * gr[0] + m[9] * gr[1] + m[6] * gr[2]);
+    }
+    F[s] = f[0];
+    F[N + s] = f[1];
+    F[2 * N + s] = f[2];
   }
 }
 
@@ -215,7 +257,7 @@ hipError_t phase_step_st(const PhaseArgs& a, hipStream_t s) {
   hipLaunchKernelGGL((flux_kernel<ST>), grid, block, 0, s, static_cast<const C*>(a.phi),
                      static_cast<const T*>(a.state), static_cast<Rec<C>*>(a.J), a.nx, a.ny, a.nz,
                      a.N, static_cast<C>(a.lambda), static_cast<C>(a.eps), a.scale[1], a.scale[2],
-                     a.scale[3]);
+                     a.scale[3], a.walls_y != 0);
   // update: 64 x 8 column tiles, z-chunks of >= 8 planes for ~512 workgroups
   const int tiles_x = (a.nx + 63) / 64, tiles_y = (a.ny + kUpdRows - 1) / kUpdRows;
   const int cols = tiles_x * tiles_y;
@@ -226,7 +268,7 @@ hipError_t phase_step_st(const PhaseArgs& a, hipStream_t s) {
   const int zchunks = (a.nz + zchunk - 1) / zchunk;
   hipLaunchKernelGGL((update_kernel<C>), dim3(cols * zchunks), dim3(64 * kUpdRows), 0, s,
                      static_cast<const Rec<C>*>(a.J), static_cast<C*>(a.phi_out), a.nx, a.ny,
-                     a.nz, static_cast<C>(a.D), tiles_x, tiles_y, zchunk);
+                     a.nz, static_cast<C>(a.D), tiles_x, tiles_y, zchunk, a.walls_y != 0);
   return hipGetLastError();
 }
 
@@ -242,20 +284,32 @@ hipError_t launch_phase_step(int storage, const PhaseArgs& a, hipStream_t s) {
   }
 }
 
-hipError_t launch_capillary_force(int storage, const PhaseArgs& a, hipStream_t s) {
+namespace {
+template <int ST>
+hipError_t force_st(const PhaseArgs& a, hipStream_t s) {
+  using C = typename Storage<ST>::C;
+  using T = typename Storage<ST>::T;
   const dim3 grid(phase_grid(a.N)), block(kPhaseThreads);
-  if (storage == kF64) {
-    hipLaunchKernelGGL((force_kernel<double>), grid, block, 0, s,
-                       static_cast<const double*>(a.phi_out), static_cast<double*>(a.F), a.nx,
-                       a.ny, a.nz, a.N, a.beta, a.kappa, a.Fb[0], a.Fb[1], a.Fb[2]);
-  } else {
-    hipLaunchKernelGGL((force_kernel<float>), grid, block, 0, s,
-                       static_cast<const float*>(a.phi_out), static_cast<float*>(a.F), a.nx,
-                       a.ny, a.nz, a.N, static_cast<float>(a.beta), static_cast<float>(a.kappa),
-                       static_cast<float>(a.Fb[0]), static_cast<float>(a.Fb[1]),
-                       static_cast<float>(a.Fb[2]));
-  }
+  if (a.contrast)
+    hipLaunchKernelGGL((force_kernel<ST, true>), grid, block, 0, s,
+                       static_cast<const C*>(a.phi_out), static_cast<const T*>(a.state),
+                       static_cast<C*>(a.F), a.nx, a.ny, a.nz, a.N, a);
+  else
+    hipLaunchKernelGGL((force_kernel<ST, false>), grid, block, 0, s,
+                       static_cast<const C*>(a.phi_out), static_cast<const T*>(a.state),
+                       static_cast<C*>(a.F), a.nx, a.ny, a.nz, a.N, a);
   return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_capillary_force(int storage, const PhaseArgs& a, hipStream_t s) {
+  switch (storage) {
+    case kF64: return force_st<kF64>(a, s);
+    case kF32: return force_st<kF32>(a, s);
+    case kF16S: return force_st<kF16S>(a, s);
+    case kBF16S: return force_st<kBF16S>(a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace lbf

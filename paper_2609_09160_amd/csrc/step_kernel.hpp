@@ -76,9 +76,13 @@ __device__ __forceinline__ void finalize(const Sums<C>& S, C Fx, C Fy, C Fz, C o
 // populations, and a destination writes its 10 new moments.  FNEXT: the force
 // changes every step (two-component flow); the source uses F(t) and the
 // correction of Eq. (8) at the destination uses F(t+1) from a second field.
-template <int Q_, int ST, bool FFIELD, bool FNEXT = false>
+// VAR: density and viscosity follow the phase field (section 2): the source
+// relaxes with omega(phi(t)) and applies F(t) / rho(phi(t)), the correction
+// applies F(t+1) / rho(phi(t+1)).
+template <int Q_, int ST, bool FFIELD, bool FNEXT = false, bool VAR = false>
 struct Forward {
   static_assert(FFIELD || !FNEXT, "a time-dependent force is a force field");
+  static_assert(FNEXT || !VAR, "variable properties come with the two-component force");
   static constexpr int Q = Q_;
   using S = Storage<ST>;
   using C = typename S::C;
@@ -90,6 +94,7 @@ struct Forward {
     T m[10];
     C F[3];
     C Fn[(FNEXT && OWN) ? 3 : 1];
+    C ph[VAR ? (OWN ? 2 : 1) : 1];  // phi(t), and phi(t+1) at destinations
   };
   // force of the correction at the site (F(t), or F(t+1) when it changes)
   struct Carry {
@@ -131,6 +136,17 @@ struct Forward {
         for (int s = 0; s < NS; ++s) r[s].Fn[k] = v[s];
       }
     }
+    if constexpr (VAR) {
+      const C* __restrict__ ph[2] = {static_cast<const C*>(a.phi_src),
+                                     static_cast<const C*>(a.phi_dst)};
+#pragma unroll
+      for (int k = 0; k < (OWN ? 2 : 1); ++k) {
+        C v[NS];
+        buf_load_n<C, NS>(plane_rsrc(ph[k] + pb, plane_bytes * kFscale), off * kFscale, v);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) r[s].ph[k] = v[s];
+      }
+    }
   }
 
   template <bool OWN>
@@ -146,14 +162,32 @@ struct Forward {
     C F[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) F[k] = FFIELD ? r.F[k] : static_cast<C>(a.F[k]);
+    C omega = static_cast<C>(a.omega);
+    if constexpr (VAR) {
+      // F / rho and omega of phi(t) at the source, F(t+1) / rho(phi(t+1))
+      // for the correction at the destination
+      const C p = r.ph[0];
+      const C inv_rho = C(1) / (static_cast<C>(a.rho_l) + p * static_cast<C>(a.rho_h - a.rho_l));
+      const C nu = static_cast<C>(a.nu_l) + p * static_cast<C>(a.nu_h - a.nu_l);
+      omega = C(1) / (C(3) * nu + C(0.5));
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      if constexpr (FNEXT && OWN)
-        c.F[k] = r.Fn[k];
-      else
-        c.F[k] = F[k];
+      for (int k = 0; k < 3; ++k) F[k] *= inv_rho;
+      if constexpr (OWN) {
+        const C inv_rho_d =
+            C(1) / (static_cast<C>(a.rho_l) + r.ph[1] * static_cast<C>(a.rho_h - a.rho_l));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) c.F[k] = r.Fn[k] * inv_rho_d;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if constexpr (FNEXT && OWN)
+          c.F[k] = r.Fn[k];
+        else
+          c.F[k] = F[k];
+      }
     }
-    source_pops<Q, C>(m, F[0], F[1], F[2], static_cast<C>(a.omega), g);
+    source_pops<Q, C>(m, F[0], F[1], F[2], omega, g);
   }
 
   template <int NS>
@@ -187,9 +221,12 @@ struct Forward {
 
 template <int Q, int ST, int TY, bool WALLY, bool FFIELD>
 hipError_t launch_step_t(const StepArgs& a, hipStream_t stream) {
-  if constexpr (FFIELD && !WALLY) {
-    // a force that changes every step (two-component flow; periodic only)
-    if (a.Fnext) return launch_march<Forward<Q, ST, true, true>, TY, false>(a, stream);
+  if constexpr (FFIELD && TY <= 8) {
+    // a force that changes every step (two-component flow), with or without
+    // density and viscosity contrast
+    if (a.Fnext && a.phi_src)
+      return launch_march<Forward<Q, ST, true, true, true>, TY, WALLY>(a, stream);
+    if (a.Fnext) return launch_march<Forward<Q, ST, true, true>, TY, WALLY>(a, stream);
   }
   if (a.Fnext) return hipErrorInvalidValue;
   return launch_march<Forward<Q, ST, FFIELD>, TY, WALLY>(a, stream);
