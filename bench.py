@@ -4,11 +4,15 @@
 Default workload: D3Q19, FP32 moment storage, 512^3 periodic, tau = 0.6,
 random solenoidal initial field (|k| <= 8, rms |u| = 0.02, seed 9160).  One
 "step" is one fused stream-and-collide update of every site (one kernel
-launch).  Prints ONE JSON line.
+launch).  Prints ONE JSON line: the main workload's MLUPS and HBM roofline
+fraction (with the calibrated counter traffic when it matches the kernel
+sources), the measured copy ceiling, energy per update, the D3Q27 / 16-bit /
+FP64 variants, the discrete adjoint (192^3) and the two-component droplet
+(256^3, equal phases and with contrast), and the CPU oracle baseline.
 
   python bench.py [--steps K] [--warmup W] [--lattice 19|27]
                   [--storage f32|f64|f16s|bf16s] [--n 512] [--no-variants]
-                  [--no-cpu-baseline] [--copy-probe]
+                  [--no-adjoint] [--no-cpu-baseline] [--copy-probe]
 """
 import argparse
 import hashlib

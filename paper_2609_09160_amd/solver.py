@@ -126,8 +126,11 @@ class Solver:
 
     # -- two-component variant -------------------------------------------------------
     def enable_two_phase(self, sigma, width, diffusivity, rho=(1.0, 1.0), tau=None):
-        """Phase field by the conservative Allen-Cahn equation plus capillary
-        force (equal densities and viscosities)."""
+        """Two-component variant: phase field by the conservative Allen-Cahn
+        equation, capillary force, and densities rho = (light, heavy) and
+        relaxation times tau = (light, heavy) blended in the phase field
+        (tau: one value for both phases, default the solver's tau).  The
+        solver's uniform force is read as a body acceleration."""
         pp = _lib.LbfastPhaseParams()
         pp.struct_size = ctypes.sizeof(_lib.LbfastPhaseParams)
         pp.sigma, pp.width, pp.diffusivity = float(sigma), float(width), float(diffusivity)
