@@ -71,17 +71,31 @@ def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
+D3Q27H = 270  # lattice code: the D3Q27 velocity set with the complete Hermite basis
+
+
+def lattice_code(Q):
+    """(code for the C library, number of velocities) of 19, 27 or "27h"."""
+    if Q in ("27h", "D3Q27h", D3Q27H):
+        return D3Q27H, 27
+    Q = int(Q)
+    if Q not in (19, 27):
+        raise ValueError(f"unknown velocity set {Q!r}")
+    return Q, Q
+
+
 def threads() -> int:
     """OpenMP threads the oracle's loops use (OMP_NUM_THREADS or all cores)."""
     return _load().oracle_threads()
 
 
-def lattice_tables(Q: int):
+def lattice_tables(Q):
     """(c[Q,3] int, w[Q] float64) of the oracle's velocity set."""
     lib = _load()
+    code, Q = lattice_code(Q)
     c = np.zeros((Q, 3), dtype=np.int32)
     w = np.zeros(Q, dtype=np.float64)
-    q = lib.oracle_lattice(Q, c.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(w))
+    q = lib.oracle_lattice(code, c.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(w))
     if q != Q:
         raise ValueError(f"unknown velocity set Q={Q}")
     return c.astype(np.int64), w
@@ -90,13 +104,14 @@ def lattice_tables(Q: int):
 class PopulationOracle:
     """Full-population FP64 regularized LBM on an (nx, ny, nz) grid.
 
-    State: populations f[Q, nz, ny, nx].  `force` is None (zero), a length-3
+    State: populations f[Q, nz, ny, nx].  `Q` is 19, 27 or "27h" (the D3Q27
+    set with the complete Hermite basis).  `force` is None (zero), a length-3
     uniform vector, or a [3, nz, ny, nx] field (static in time).  `bc` is a
     per-axis (x, y, z) tuple: 0 periodic, 1 halfway bounce-back walls.
     """
 
     def __init__(self, Q, shape, tau, bc=(0, 0, 0), force=None):
-        self.Q = int(Q)
+        self.lattice, self.Q = lattice_code(Q)
         self.nx, self.ny, self.nz = (int(v) for v in shape)
         self.N = self.nx * self.ny * self.nz
         self.tau = float(tau)
@@ -117,26 +132,26 @@ class PopulationOracle:
     def set_moments(self, m):
         """Populations whose corrected moments are m[10, nz, ny, nx] (or [10, N])."""
         m = np.ascontiguousarray(np.asarray(m, dtype=np.float64).reshape(10, self.N))
-        rc = self._lib.oracle_init(self.Q, *self._dims(), _dp(m), _dp(self.F), _dp(self.f))
+        rc = self._lib.oracle_init(self.lattice, *self._dims(), _dp(m), _dp(self.F), _dp(self.f))
         assert rc == 0
 
     def moments(self):
         """Corrected moments [10, nz, ny, nx] of the current populations."""
         m = np.zeros((10, self.N), dtype=np.float64)
-        rc = self._lib.oracle_moments(self.Q, *self._dims(), _dp(self.f), _dp(self.F), _dp(m))
+        rc = self._lib.oracle_moments(self.lattice, *self._dims(), _dp(self.f), _dp(self.F), _dp(m))
         assert rc == 0
         return m.reshape(10, self.nz, self.ny, self.nx)
 
     def step(self, n=1):
         bcp = self.bc.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
-        rc = self._lib.oracle_run(self.Q, *self._dims(), bcp, self.tau, _dp(self.F),
+        rc = self._lib.oracle_run(self.lattice, *self._dims(), bcp, self.tau, _dp(self.F),
                                   _dp(self.f), _dp(self._scratch), int(n))
         assert rc == 0
 
     def post_collision(self):
         """Post-collision populations f*[Q, N] of the current state."""
         out = np.zeros_like(self.f)
-        rc = self._lib.oracle_collide(self.Q, *self._dims(), self.tau, _dp(self.f),
+        rc = self._lib.oracle_collide(self.lattice, *self._dims(), self.tau, _dp(self.f),
                                       _dp(self.F), _dp(out))
         assert rc == 0
         return out

@@ -27,6 +27,13 @@
  *      walls in section 4 but no scheme, so this is a reading).
  * rho = 1 (one component, section 2: rho(phi) with equal phase densities).
  *
+ * D3Q27h (lattice code 270): the D3Q27 velocity set with the series of
+ * Eq. (4) run over the complete Hermite basis of D3Q27 instead of stopping at
+ * second order (section 2, the paragraph after Eq. (9)): the coefficients of
+ * orders 3 to 6 are rebuilt from u and a2neq by the recursive closures the
+ * paper cites (Shan, Yuan and Chen 2006 for the equilibrium, Malaspinas 2015
+ * for the non-equilibrium part); everything else is as above.
+ *
  * Everything is written with generic loops over directions and tensor
  * indices so that it can be checked against the equations by eye.  The
  * velocity sets are the textbook D3Q19 / D3Q27 (the paper defers to the
@@ -54,9 +61,12 @@ int oracle_threads(void) {
 
 /* Build the velocity set: enumerate {-1,0,1}^3, keep |c|^2 <= 2 for Q=19.
  * Returns Q, or -1 for an unknown Q. */
+#define D3Q27H 270
+
 int oracle_lattice(int Q, int* c, double* w) {
   double wt[4];
   int maxc2;
+  if (Q == D3Q27H) Q = 27; /* same velocity set, complete Hermite basis */
   if (Q == 19) {
     wt[0] = 1.0 / 3.0; wt[1] = 1.0 / 18.0; wt[2] = 1.0 / 36.0; wt[3] = 0.0;
     maxc2 = 2;
@@ -79,17 +89,31 @@ int oracle_lattice(int Q, int* c, double* w) {
   return q;
 }
 
+/* D3Q27h: the components of orders 3..6 of the complete basis */
+#define NHIGH 17
+
 typedef struct {
   int Q;
+  int high; /* D3Q27h: complete Hermite basis in the reconstruction */
   int c[27][3];
   double w[27];
   int opp[27];
+  /* D3Q27h: per high-order component b, its index tuple (order n[b]), the
+   * factor (number of orderings) / (cs^(2n) n!) of Eq. (4), and H_b(c_i) */
+  int hn[NHIGH];
+  int hidx[NHIGH][6];
+  double hfac[NHIGH];
+  double hH[NHIGH][27];
 } lattice_t;
 
-static int make_lattice(int Q, lattice_t* L) {
+static void make_high_order_table(lattice_t* L);
+
+static int make_lattice(int code, lattice_t* L) {
   int cc[81];
-  if (oracle_lattice(Q, cc, L->w) != Q) return -1;
+  const int Q = (code == D3Q27H) ? 27 : code;
+  if (oracle_lattice(code, cc, L->w) != Q) return -1;
   L->Q = Q;
+  L->high = (code == D3Q27H);
   for (int i = 0; i < Q; ++i)
     for (int a = 0; a < 3; ++a) L->c[i][a] = cc[3 * i + a];
   for (int i = 0; i < Q; ++i) {
@@ -99,6 +123,7 @@ static int make_lattice(int Q, lattice_t* L) {
           L->c[j][2] == -L->c[i][2])
         L->opp[i] = j;
   }
+  if (L->high) make_high_order_table(L);
   return 0;
 }
 
@@ -159,8 +184,100 @@ static double guo_source(const lattice_t* L, int i, const double u[3], const dou
   return L->w[i] * s;
 }
 
+/* ---- D3Q27h: orders 3 to 6 of the complete Hermite basis ----
+ *
+ * Hermite tensor of order n at velocity c, by the standard (Grad) recursion
+ *   H^(n)_{a1..an} = c_an H^(n-1)_{a1..an-1}
+ *                    - cs^2 sum_{k<n} d(ak, an) H^(n-2)_{a1..an-1 without ak},
+ * which gives H0 = 1, H1 = c, H2 = c c - cs^2 I of section 2 for n <= 2. */
+static double hermite_tensor(int n, const int* idx, const int c[3]) {
+  if (n == 0) return 1.0;
+  if (n == 1) return (double)c[idx[0]];
+  double h = c[idx[n - 1]] * hermite_tensor(n - 1, idx, c);
+  for (int k = 0; k < n - 1; ++k) {
+    if (idx[k] != idx[n - 1]) continue;
+    int rest[6], r = 0;
+    for (int j = 0; j < n - 1; ++j)
+      if (j != k) rest[r++] = idx[j];
+    h -= CS2 * hermite_tensor(n - 2, rest, c);
+  }
+  return h;
+}
+
+/* Equilibrium coefficient by the recursive closure of Shan et al. (athermal,
+ * velocity-based form of Eq. (6): a^(1)eq = u, a^(2)eq = u u):
+ *   a^(n)eq_{a1..an} = a^(n-1)eq_{a1..an-1} u_an. */
+static double coeff_eq(int n, const int* idx, const double u[3]) {
+  if (n == 1) return u[idx[0]];
+  return coeff_eq(n - 1, idx, u) * u[idx[n - 1]];
+}
+
+/* Non-equilibrium coefficient by the recursive regularization of
+ * Malaspinas (2015), starting from a^(2)neq = a2neq:
+ *   a^(n)neq_{a1..an} = u_an a^(n-1)neq_{a1..an-1}
+ *       + sum_{l<n} [prod_{k<n, k != l} u_ak] a^(2)neq_{al an}. */
+static double coeff_neq(int n, const int* idx, const double u[3], double a2neq[3][3]) {
+  if (n == 2) return a2neq[idx[0]][idx[1]];
+  const int an = idx[n - 1];
+  double v = u[an] * coeff_neq(n - 1, idx, u, a2neq);
+  for (int l = 0; l < n - 1; ++l) {
+    double prod = 1.0;
+    for (int k = 0; k < n - 1; ++k)
+      if (k != l) prod *= u[idx[k]];
+    v += prod * a2neq[idx[l]][an];
+  }
+  return v;
+}
+
+/* The components of orders 3..6 of the complete D3Q27 basis.  A component
+ * is fixed by how often each axis occurs (kx, ky, kz <= 2: the components in
+ * which an axis occurs three times vanish on D3Q27 or alias lower orders and
+ * are not part of the basis); in the full contraction of Eq. (4) it occurs
+ * n! / (kx! ky! kz!) times. */
+static void make_high_order_table(lattice_t* L) {
+  int b = 0;
+  for (int kx = 0; kx <= 2; ++kx)
+    for (int ky = 0; ky <= 2; ++ky)
+      for (int kz = 0; kz <= 2; ++kz) {
+        const int n = kx + ky + kz;
+        if (n < 3) continue;
+        int r = 0;
+        for (int k = 0; k < kx; ++k) L->hidx[b][r++] = 0;
+        for (int k = 0; k < ky; ++k) L->hidx[b][r++] = 1;
+        for (int k = 0; k < kz; ++k) L->hidx[b][r++] = 2;
+        double nfact = 1.0, cs2n = 1.0;
+        for (int k = 2; k <= n; ++k) nfact *= k;
+        for (int k = 0; k < n; ++k) cs2n *= CS2;
+        const double fk[3] = {1.0, 1.0, 2.0}; /* 0!, 1!, 2! */
+        const double orderings = nfact / (fk[kx] * fk[ky] * fk[kz]);
+        L->hn[b] = n;
+        L->hfac[b] = orderings / (cs2n * nfact);
+        for (int i = 0; i < L->Q; ++i) L->hH[b][i] = hermite_tensor(n, L->hidx[b], L->c[i]);
+        ++b;
+      }
+}
+
+/* Orders 3..6 at one site, added to the populations:
+ * fpost_i += w_i sum_b H_b(c_i) [a_b eq + (1 - omega) a_b neq] (times the
+ * factor of the component). */
+static void add_high_order_terms(const lattice_t* L, const double u[3], double a2neq[3][3],
+                                 double omega, double* fpost) {
+  double coef[NHIGH];
+  for (int b = 0; b < NHIGH; ++b) {
+    const int n = L->hn[b];
+    coef[b] = L->hfac[b] * (coeff_eq(n, L->hidx[b], u) +
+                            (1.0 - omega) * coeff_neq(n, L->hidx[b], u, a2neq));
+  }
+  for (int i = 0; i < L->Q; ++i) {
+    double sum = 0.0;
+    for (int b = 0; b < NHIGH; ++b) sum += L->hH[b][i] * coef[b];
+    fpost[i] += L->w[i] * sum;
+  }
+}
+
 /* Step 3 at one site: regularized post-collision populations, Eq. (3) with
- * f^eq, f^neq from Eq. (4) and the coefficients of Eq. (6). */
+ * f^eq, f^neq from Eq. (4) and the coefficients of Eq. (6) (D3Q27h: plus the
+ * orders 3 to 6 of the complete basis). */
 static void site_collide(const lattice_t* L, const double m[10], const double F[3],
                          double rho, double omega, double* fpost) {
   double u[3] = {m[1], m[2], m[3]};
@@ -178,6 +295,7 @@ static void site_collide(const lattice_t* L, const double m[10], const double F[
     double S = guo_source(L, i, u, F, rho);
     fpost[i] = feq + (1.0 - omega) * fneq + 0.5 * S;
   }
+  if (L->high) add_high_order_terms(L, u, a2neq, omega, fpost);
 }
 
 static void site_force(const double* F, int64_t N, int64_t s, double out[3]) {
@@ -191,10 +309,11 @@ static void site_force(const double* F, int64_t N, int64_t s, double out[3]) {
 /* Populations whose corrected moments (step 1) are exactly m:
  * f_i = w_i [a0 + c.(u - F/2rho)/cs^2 + H2:(a2 - (Fu+uF)/2rho)/(2 cs^4)],
  * i.e. Eq. (4) with the correction of Eq. (8) undone. */
-int oracle_init(int Q, int64_t nx, int64_t ny, int64_t nz, const double* m,
+int oracle_init(int lat, int64_t nx, int64_t ny, int64_t nz, const double* m,
                 const double* F, double* f) {
   lattice_t L;
-  if (make_lattice(Q, &L)) return -1;
+  if (make_lattice(lat, &L)) return -1;
+  const int Q = L.Q;
   const int64_t N = nx * ny * nz;
   const double rho = 1.0;
 #pragma omp parallel for schedule(static)
@@ -214,10 +333,11 @@ int oracle_init(int Q, int64_t nx, int64_t ny, int64_t nz, const double* m,
 }
 
 /* Reported (corrected) moments of a population field: step 1 at every site. */
-int oracle_moments(int Q, int64_t nx, int64_t ny, int64_t nz, const double* f,
+int oracle_moments(int lat, int64_t nx, int64_t ny, int64_t nz, const double* f,
                    const double* F, double* m) {
   lattice_t L;
-  if (make_lattice(Q, &L)) return -1;
+  if (make_lattice(lat, &L)) return -1;
+  const int Q = L.Q;
   const int64_t N = nx * ny * nz;
 #pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < N; ++s) {
@@ -231,10 +351,11 @@ int oracle_moments(int Q, int64_t nx, int64_t ny, int64_t nz, const double* f,
 }
 
 /* Steps 1-3 at every site: fpost = collide(moments(f)). */
-int oracle_collide(int Q, int64_t nx, int64_t ny, int64_t nz, double tau,
+int oracle_collide(int lat, int64_t nx, int64_t ny, int64_t nz, double tau,
                    const double* f, const double* F, double* fpost) {
   lattice_t L;
-  if (make_lattice(Q, &L)) return -1;
+  if (make_lattice(lat, &L)) return -1;
+  const int Q = L.Q;
   const int64_t N = nx * ny * nz;
   const double omega = 1.0 / tau;
 #pragma omp parallel for schedule(static)
@@ -251,10 +372,11 @@ int oracle_collide(int Q, int64_t nx, int64_t ny, int64_t nz, double tau,
 
 /* Step 4: pull streaming with periodic wrap, or halfway bounce-back where the
  * source lies beyond a wall (bc[a] = 1 on axis a). */
-int oracle_stream(int Q, int64_t nx, int64_t ny, int64_t nz, const int* bc,
+int oracle_stream(int lat, int64_t nx, int64_t ny, int64_t nz, const int* bc,
                   const double* fpost, double* f) {
   lattice_t L;
-  if (make_lattice(Q, &L)) return -1;
+  if (make_lattice(lat, &L)) return -1;
+  const int Q = L.Q;
   const int64_t n[3] = {nx, ny, nz};
   const int64_t N = nx * ny * nz;
 #pragma omp parallel for schedule(static)
@@ -285,11 +407,11 @@ int oracle_stream(int Q, int64_t nx, int64_t ny, int64_t nz, const int* bc,
 }
 
 /* nsteps full steps on f (in place); scratch holds Q x N doubles. */
-int oracle_run(int Q, int64_t nx, int64_t ny, int64_t nz, const int* bc, double tau,
+int oracle_run(int lat, int64_t nx, int64_t ny, int64_t nz, const int* bc, double tau,
                const double* F, double* f, double* scratch, int64_t nsteps) {
   for (int64_t t = 0; t < nsteps; ++t) {
-    if (oracle_collide(Q, nx, ny, nz, tau, f, F, scratch)) return -1;
-    if (oracle_stream(Q, nx, ny, nz, bc, scratch, f)) return -1;
+    if (oracle_collide(lat, nx, ny, nz, tau, f, F, scratch)) return -1;
+    if (oracle_stream(lat, nx, ny, nz, bc, scratch, f)) return -1;
   }
   return 0;
 }
@@ -494,10 +616,11 @@ int oracle_contrast_force(int64_t nx, int64_t ny, int64_t nz, const int* bc, con
 
 /* Steps 1-3 with a relaxation rate and a density per site (omega, rho: N
  * values each): fpost = collide(moments(f)). */
-int oracle_collide_var(int Q, int64_t nx, int64_t ny, int64_t nz, const double* omega,
+int oracle_collide_var(int lat, int64_t nx, int64_t ny, int64_t nz, const double* omega,
                        const double* rho, const double* f, const double* F, double* fpost) {
   lattice_t L;
-  if (make_lattice(Q, &L)) return -1;
+  if (make_lattice(lat, &L)) return -1;
+  const int Q = L.Q;
   const int64_t N = nx * ny * nz;
 #pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < N; ++s) {
@@ -512,10 +635,11 @@ int oracle_collide_var(int Q, int64_t nx, int64_t ny, int64_t nz, const double* 
 }
 
 /* Reported moments with a density per site in the correction of Eq. (8). */
-int oracle_moments_var(int Q, int64_t nx, int64_t ny, int64_t nz, const double* rho,
+int oracle_moments_var(int lat, int64_t nx, int64_t ny, int64_t nz, const double* rho,
                        const double* f, const double* F, double* m) {
   lattice_t L;
-  if (make_lattice(Q, &L)) return -1;
+  if (make_lattice(lat, &L)) return -1;
+  const int Q = L.Q;
   const int64_t N = nx * ny * nz;
 #pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < N; ++s) {
@@ -529,10 +653,11 @@ int oracle_moments_var(int Q, int64_t nx, int64_t ny, int64_t nz, const double* 
 }
 
 /* Populations whose corrected moments (density per site) are exactly m. */
-int oracle_init_var(int Q, int64_t nx, int64_t ny, int64_t nz, const double* rho,
+int oracle_init_var(int lat, int64_t nx, int64_t ny, int64_t nz, const double* rho,
                     const double* m, const double* F, double* f) {
   lattice_t L;
-  if (make_lattice(Q, &L)) return -1;
+  if (make_lattice(lat, &L)) return -1;
+  const int Q = L.Q;
   const int64_t N = nx * ny * nz;
 #pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < N; ++s) {

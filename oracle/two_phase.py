@@ -125,7 +125,7 @@ class TwoPhaseOracle:
         nx, ny, nz = self.shape
         m = np.zeros((10, self.N))
         r = np.ascontiguousarray(self.rho(self.phi).reshape(self.N))
-        assert _load().oracle_moments_var(self.flow.Q, nx, ny, nz, _dp(r), _dp(self.flow.f),
+        assert _load().oracle_moments_var(self.flow.lattice, nx, ny, nz, _dp(r), _dp(self.flow.f),
                                           _dp(self.flow.F), _dp(m)) == 0
         return m
 
@@ -137,7 +137,7 @@ class TwoPhaseOracle:
         m = np.ascontiguousarray(np.asarray(m, dtype=np.float64).reshape(10, self.N))
         self.flow.F = self._force(self.phi, m)
         r = np.ascontiguousarray(self.rho(self.phi).reshape(self.N))
-        assert _load().oracle_init_var(self.flow.Q, nx, ny, nz, _dp(r), _dp(m),
+        assert _load().oracle_init_var(self.flow.lattice, nx, ny, nz, _dp(r), _dp(m),
                                        _dp(self.flow.F), _dp(self.flow.f)) == 0
 
     def moments(self):
@@ -155,9 +155,9 @@ class TwoPhaseOracle:
             F_new = self._force(phi_new, m)
             om = np.ascontiguousarray(self.omega(self.phi).reshape(self.N))
             r = np.ascontiguousarray(self.rho(self.phi).reshape(self.N))
-            assert lib.oracle_collide_var(self.flow.Q, nx, ny, nz, _dp(om), _dp(r),
+            assert lib.oracle_collide_var(self.flow.lattice, nx, ny, nz, _dp(om), _dp(r),
                                           _dp(self.flow.f), _dp(self.flow.F), _dp(post)) == 0
-            assert lib.oracle_stream(self.flow.Q, nx, ny, nz, bp, _dp(post),
+            assert lib.oracle_stream(self.flow.lattice, nx, ny, nz, bp, _dp(post),
                                      _dp(self.flow.f)) == 0
             self.phi, self.flow.F = phi_new, F_new
 

@@ -54,7 +54,7 @@ def test_projection_inverts_reconstruction(oracle_mod, Q):
     assert np.abs(o.moments() - m).max() <= 1e-16
 
 
-@pytest.mark.parametrize("Q", [19, 27])
+@pytest.mark.parametrize("Q", [19, 27, "27h"])
 def test_fixed_points(oracle_mod, Q):
     """Rest state and any uniform flow at equilibrium are steady (F = 0).
     Catches a relaxation applied to the equilibrium part, or a streaming
@@ -69,7 +69,7 @@ def test_fixed_points(oracle_mod, Q):
         assert np.abs(o.moments() - m).max() <= 1e-16
 
 
-@pytest.mark.parametrize("Q", [19, 27])
+@pytest.mark.parametrize("Q", [19, 27, "27h"])
 def test_uniform_force_closed_form(oracle_mod, Q):
     """Uniform state, uniform force, periodic: p* constant, u(t) = u0 + t F and
     a2(t) = u(t) u(t) exactly.  This pins Eq. (8)'s reading (updated velocity
@@ -91,7 +91,7 @@ def test_uniform_force_closed_form(oracle_mod, Q):
     assert np.abs(got - want).max() <= 1e-15
 
 
-@pytest.mark.parametrize("Q", [19, 27])
+@pytest.mark.parametrize("Q", [19, 27, "27h"])
 @pytest.mark.parametrize("bc", [(0, 0, 0), (0, 1, 0)])
 def test_conservation(oracle_mod, Q, bc):
     """sum p* is invariant (periodic and bounce-back); periodic:
@@ -112,7 +112,7 @@ def test_conservation(oracle_mod, Q, bc):
             assert abs(m5[1 + a].sum() - want) <= 1e-13 * np.abs(m0[1 + a]).sum()
 
 
-@pytest.mark.parametrize("Q", [19, 27])
+@pytest.mark.parametrize("Q", [19, 27, "27h"])
 def test_shear_wave_exact_discrete(oracle_mod, Q):
     """Linear shear wave u_x = U sin(ky), a2_xy = Q cos(ky): the discrete update
     is [U, Q](t+1) = M [U, Q](t) with
@@ -142,7 +142,7 @@ def test_shear_wave_exact_discrete(oracle_mod, Q):
     assert abs(ratio - 1) < 1e-2
 
 
-@pytest.mark.parametrize("Q", [19, 27])
+@pytest.mark.parametrize("Q", [19, 27, "27h"])
 def test_taylor_green_decay(oracle_mod, Q):
     """Section 4: E(t)/E(0) = exp(-6 nu k^2 t), k = 2 pi / N, for the vortex of
     Eq. (11).  32^3, tau = 0.8 (nu = 0.1), U0 = 0.01; fit over t in [20, 200].
@@ -163,7 +163,7 @@ def test_taylor_green_decay(oracle_mod, Q):
     assert abs(nu_fit / nu - 1) < 1e-2
 
 
-@pytest.mark.parametrize("Q", [19, 27])
+@pytest.mark.parametrize("Q", [19, 27, "27h"])
 @pytest.mark.parametrize("tau", [0.6, 0.9])
 def test_poiseuille(oracle_mod, Q, tau):
     """Body-force-driven channel between halfway bounce-back walls (y) reaches
