@@ -63,8 +63,15 @@ enum {
   LBF_E_STATE = -6        /* call not valid in the handle's current state */
 };
 
-/* velocity sets, both truncated at second order (section 2, last paragraphs) */
-enum { LBF_D3Q19 = 19, LBF_D3Q27 = 27 };
+/* velocity sets (section 2, the paragraph after Eq. (9)).  LBF_D3Q19 and
+ * LBF_D3Q27: Hermite series truncated at second order.  LBF_D3Q27H: the D3Q27
+ * set with the series over its complete Hermite basis (orders up to 6), the
+ * coefficients of order >= 3 rebuilt every step from u and a2 - u u by the
+ * recursive closures the paper cites (Shan et al. for the equilibrium,
+ * Malaspinas for the non-equilibrium part); the stored fields, the projection
+ * and the correction are those of the other sets.  Its value is a code, not
+ * a velocity count.  The adjoint covers LBF_D3Q19 and LBF_D3Q27 only. */
+enum { LBF_D3Q19 = 19, LBF_D3Q27 = 27, LBF_D3Q27H = 270 };
 
 /* element types: storage of the moment planes, and dtype of user arrays.
  * F16S/BF16S = 16-bit storage of v/s_m with a power-of-two scale s_m per
@@ -80,7 +87,7 @@ enum { LBF_PERIODIC = 0, LBF_WALLS = 1 };
 
 typedef struct lbfast_params {
   uint32_t struct_size; /* = sizeof(lbfast_params) */
-  int32_t lattice;      /* LBF_D3Q19 or LBF_D3Q27 */
+  int32_t lattice;      /* LBF_D3Q19, LBF_D3Q27 or LBF_D3Q27H */
   int32_t storage;      /* LBF_F64, LBF_F32, LBF_F16S, LBF_BF16S */
   int32_t bc[3];        /* per axis x, y, z: LBF_PERIODIC or LBF_WALLS */
   int64_t nx, ny, nz;   /* grid, each >= 1 (>= 2 on a walled axis) */
@@ -142,7 +149,8 @@ int lbfast_state_ptr(lbfast_t h, void** dev_ptr);
 int lbfast_get_scales(lbfast_t h, float out[10]);
 
 /* Launch shape: rows per tile (4, 6, 8 or 14 -- at most 8 with two sites
- * per lane; LBF_E_UNSUPPORTED if the tile's LDS would exceed 160 KiB) and z-planes per workgroup (>= 1); 0 keeps
+ * per lane or with LBF_D3Q27H; LBF_E_UNSUPPORTED if the tile's LDS would
+ * exceed 160 KiB) and z-planes per workgroup (>= 1); 0 keeps
  * the current value.  Every shape computes the same formulas per site; the
  * tile heights are separately compiled, so results may differ between shapes
  * in the last bits (floating-point contraction), while one shape is bitwise
@@ -198,7 +206,8 @@ int lbfast_get_phase(lbfast_t h, void* phi, int dtype, int on_device);
 
 /* Discrete adjoint (the paper does not treat differentiation; this is the
  * exact reverse mode of the discrete step of Eqs. (7)-(9) as implemented by
- * lbfast_step, for F64 and F32 storage; LBF_E_UNSUPPORTED for 16-bit).
+ * lbfast_step, for F64 and F32 storage and the lattices LBF_D3Q19 and
+ * LBF_D3Q27; LBF_E_UNSUPPORTED for 16-bit storage and for LBF_D3Q27H).
  * The objective J is any function of the final state m(T); the caller gives
  * lambda_T = dJ/dm(T) and receives dJ/dF (gradient with respect to the
  * per-site force field, static in time) and optionally dJ/dm(0).  Gradients

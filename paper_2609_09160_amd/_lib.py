@@ -14,11 +14,13 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "lbfast.h")
 # constants mirrored from include/lbfast.h
 LBF_OK, LBF_E_ARG, LBF_E_UNSUPPORTED, LBF_E_NOMEM = 0, -1, -2, -3
 LBF_E_DEVICE, LBF_E_NONFINITE, LBF_E_STATE = -4, -5, -6
-LBF_D3Q19, LBF_D3Q27 = 19, 27
+LBF_D3Q19, LBF_D3Q27, LBF_D3Q27H = 19, 27, 270
 LBF_F64, LBF_F32, LBF_F16S, LBF_BF16S = 0, 1, 2, 3
 LBF_PERIODIC, LBF_WALLS = 0, 1
 
 STORAGE = {"f64": LBF_F64, "f32": LBF_F32, "f16s": LBF_F16S, "bf16s": LBF_BF16S}
+LATTICE = {19: LBF_D3Q19, 27: LBF_D3Q27, "19": LBF_D3Q19, "27": LBF_D3Q27, "27h": LBF_D3Q27H,
+           LBF_D3Q27H: LBF_D3Q27H}
 STATUS_NAMES = {0: "LBF_OK", -1: "LBF_E_ARG", -2: "LBF_E_UNSUPPORTED", -3: "LBF_E_NOMEM",
                 -4: "LBF_E_DEVICE", -5: "LBF_E_NONFINITE", -6: "LBF_E_STATE"}
 
@@ -109,7 +111,7 @@ def make_params(shape, tau, lattice=19, storage="f32", bc=(0, 0, 0), force=(0.0,
                 scale=None):
     p = LbfastParams()
     p.struct_size = ctypes.sizeof(LbfastParams)
-    p.lattice = int(lattice)
+    p.lattice = LATTICE.get(lattice, lattice if isinstance(lattice, int) else -1)
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     for a in range(3):
         p.bc[a] = int(bc[a])

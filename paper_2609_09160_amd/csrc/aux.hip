@@ -12,9 +12,23 @@ hipError_t launch_step_f32(int, int, bool, bool, const StepArgs&, hipStream_t);
 hipError_t launch_step_f16s(int, int, bool, bool, const StepArgs&, hipStream_t);
 hipError_t launch_step_bf16s(int, int, bool, bool, const StepArgs&, hipStream_t);
 
+hipError_t launch_step_h_f64(int, bool, bool, const StepArgs&, hipStream_t);
+hipError_t launch_step_h_f32(int, bool, bool, const StepArgs&, hipStream_t);
+hipError_t launch_step_h_f16s(int, bool, bool, const StepArgs&, hipStream_t);
+hipError_t launch_step_h_bf16s(int, bool, bool, const StepArgs&, hipStream_t);
+
 hipError_t launch_step(int Q, int storage, int tile_rows, bool walls_y, const StepArgs& a,
                        hipStream_t stream) {
   const bool ff = a.Ffield != nullptr;
+  if (Q == kD3Q27H) {
+    switch (storage) {
+      case kF64: return launch_step_h_f64(tile_rows, walls_y, ff, a, stream);
+      case kF32: return launch_step_h_f32(tile_rows, walls_y, ff, a, stream);
+      case kF16S: return launch_step_h_f16s(tile_rows, walls_y, ff, a, stream);
+      case kBF16S: return launch_step_h_bf16s(tile_rows, walls_y, ff, a, stream);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (storage) {
     case kF64: return launch_step_f64(Q, tile_rows, walls_y, ff, a, stream);
     case kF32: return launch_step_f32(Q, tile_rows, walls_y, ff, a, stream);

@@ -63,6 +63,12 @@ struct Lat {
     return r;
   }
   static constexpr int NB = (Q == 19) ? 5 : 9;  // directions with c_y == +1 (or -1)
+  // index of the direction with velocity (x, y, z), or -1
+  static constexpr int index(int x, int y, int z) {
+    for (int j = 0; j < Q; ++j)
+      if (cx(j) == x && cy(j) == y && cz(j) == z) return j;
+    return -1;
+  }
 };
 
 // compile-time loop: f(std::integral_constant<int, i>) for i = 0..N-1
@@ -92,6 +98,10 @@ __device__ __forceinline__ C div_by(C x) {
 
 // storage codecs: element type in HBM (T) and compute type (C)
 enum { kF64 = 0, kF32 = 1, kF16S = 2, kBF16S = 3 };
+
+// lattice code of the D3Q27 set with the complete Hermite basis (the public
+// LBF_D3Q27H); the two truncated sets go by their velocity counts, 19 and 27
+constexpr int kD3Q27H = 270;
 
 // Plane accesses go through buffer resources: one scalar descriptor per
 // x-y plane (base, byte size) plus a 32-bit per-lane byte offset.  Each access

@@ -54,8 +54,9 @@ int validate(const lbfast_params* p) {
   if (p->struct_size != sizeof(lbfast_params))
     return fail(LBF_E_ARG, "params.struct_size = %u, expected %zu", p->struct_size,
                 sizeof(lbfast_params));
-  if (p->lattice != LBF_D3Q19 && p->lattice != LBF_D3Q27)
-    return fail(LBF_E_ARG, "lattice must be 19 or 27 (got %d)", p->lattice);
+  if (p->lattice != LBF_D3Q19 && p->lattice != LBF_D3Q27 && p->lattice != LBF_D3Q27H)
+    return fail(LBF_E_ARG, "lattice must be LBF_D3Q19, LBF_D3Q27 or LBF_D3Q27H (got %d)",
+                p->lattice);
   if (elem_bytes(p->storage) == 0) return fail(LBF_E_ARG, "unknown storage %d", p->storage);
   const int64_t n[3] = {p->nx, p->ny, p->nz};
   for (int a = 0; a < 3; ++a) {
@@ -134,13 +135,17 @@ constexpr size_t kLdsLimit = 160 * 1024;
 // default launch shape (measured on MI355X at 512^3): two x-sites per lane
 // where nx allows it (even, at least one 128-wide tile), 8-row tiles (FP64:
 // 4 rows with two sites per lane, 6 with one) or the tallest that fits the
-// LDS; z-chunks only when the column tiles alone give too few workgroups
+// LDS; z-chunks only when the column tiles alone give too few workgroups.
+// D3Q27h is bound by its arithmetic: one site per lane (8 rows, FP64 6) except
+// with 16-bit storage, where two sites per lane measured faster.
 void default_launch(lbfast_ctx* h) {
   // two sites per lane unless 128-wide tiles would leave more of the last
   // tile empty than 64-wide ones
   const int64_t waste1 = ceil_div(h->p.nx, 64) * 64 - h->p.nx;
   const int64_t waste2 = ceil_div(h->p.nx, 128) * 128 - h->p.nx;
   h->lane_sites = (h->p.nx % 2 == 0 && h->p.nx >= 128 && waste2 <= waste1) ? 2 : 1;
+  const bool bits16 = h->p.storage == LBF_F16S || h->p.storage == LBF_BF16S;
+  if (h->p.lattice == LBF_D3Q27H && !bits16) h->lane_sites = 1;
   h->tile_rows = 4;
   const bool f64 = h->p.storage == LBF_F64;
   for (int ty : {f64 ? (h->lane_sites == 2 ? 4 : 6) : 8, 6, 4})
@@ -276,6 +281,8 @@ int check_adjoint_args(const lbfast_ctx* h, int64_t nsteps, int64_t every) {
     return fail(LBF_E_UNSUPPORTED, "the adjoint does not cover the two-component variant");
   if (h->p.storage != LBF_F64 && h->p.storage != LBF_F32)
     return fail(LBF_E_UNSUPPORTED, "the adjoint supports F64 and F32 storage only");
+  if (h->p.lattice == LBF_D3Q27H)
+    return fail(LBF_E_UNSUPPORTED, "the adjoint covers the second-order sets D3Q19 and D3Q27");
   if (nsteps < 0) return fail(LBF_E_ARG, "nsteps must be >= 0");
   if (every < 1) return fail(LBF_E_ARG, "every must be >= 1");
   return LBF_OK;
@@ -542,6 +549,8 @@ int lbfast_set_launch(lbfast_t h, int tile_rows, int z_chunk) {
     if (!ok) return fail(LBF_E_ARG, "tile_rows %d not supported (4, 6, 8 or 14)", tile_rows);
     if (h->lane_sites == 2 && tile_rows > 8)
       return fail(LBF_E_UNSUPPORTED, "two x-sites per lane support tiles of at most 8 rows");
+    if (h->p.lattice == LBF_D3Q27H && tile_rows > 8)
+      return fail(LBF_E_UNSUPPORTED, "D3Q27h supports tiles of at most 8 rows");
     const size_t lb = lds_bytes(h->p.lattice, h->p.storage, tile_rows, h->lane_sites);
     if (lb > kLdsLimit)
       return fail(LBF_E_UNSUPPORTED, "tile_rows %d needs %zu bytes of LDS (limit 160 KiB)",

@@ -17,6 +17,8 @@
 //      s2 = sum c c f - cs^2 s0 I;
 //   5. the correction of Eq. (8) with F at x: u = s1 + F/2,
 //      a2 = s2 + (F u + u F)/2 (updated u), a0 = s0.
+// D3Q27h (kD3Q27H) replaces step 2's second-order series by the complete
+// D3Q27 Hermite basis (source_pops_full below); steps 3-5 are unchanged.
 //
 // The launch is the z-march of march.hpp (LDS-staged pull, populations never
 // stored) with the Forward policy below.
@@ -46,6 +48,92 @@ __device__ __forceinline__ void source_pops(const C m[10], C Fx, C Fy, C Fz, C o
   const C Dx = C(4.5) * P2xx, Dy = C(4.5) * P2yy, Dz = C(4.5) * P2zz;
   const C Oxy = C(9) * P2xy, Oxz = C(9) * P2xz, Oyz = C(9) * P2yz;
   expand<Q, C>(A, Dx, Dy, Dz, Oxy, Oxz, Oyz, Vx, Vy, Vz, g);
+}
+
+// D3Q27h, steps 1-2 over the complete Hermite basis of D3Q27 (section 2,
+// after Eq. (9): orders up to 6, coefficients of order >= 3 by the recursive
+// closures of Shan et al. and Malaspinas).  Evaluated in tensor-product form
+// rather than order by order: on D3Q27 the complete basis factorises per axis,
+// the equilibrium coefficients u...u make the equilibrium part the product
+// G_i = prod_a g(c_ia; u_a) of D1Q3 equilibria (unit density), and the
+// recursive non-equilibrium closure, a sum over index pairs of a2neq times the
+// remaining velocities, makes the relaxed part (1 - omega) (1/2) B : grad_u
+// grad_u G_i with B = a2 - u u.  So
+//   f_i = w_i p* + (G_i - w_i) + (1 - omega) N_i + S_i / 2,
+// S_i the Guo term of Eq. (9) (orders 1 and 2 only).
+//
+// Per axis, scaled by 3 so that a product of three factors carries the 1/D
+// units (D = 27), at c = -1, 0, 1 (array index c + 1):
+//   W = 3 w1d(c)                  (1/2, 2, 1/2)
+//   e = 3 g(c; u) - W             (3/2 (u^2 - u), -3 u^2, 3/2 (u^2 + u))
+//   E = W + e,  d = 3 dg/du       (3 u - 3/2, -6 u, 3 u + 3/2)
+//   s = (3/2) d2g/du2             (3/2, -3, 3/2).
+// For one (c_x, c_y) column the three populations c_z = -1, 0, 1 are a
+// quadratic in c_z, K0 + K1 c_z + K2 c_z^2; gathering the z factors' values
+// into that form gives, with the column coefficients
+//   Exy = E_x E_y,  P = E_x E_y - W_x W_y = e_x E_y + W_x e_y,
+//   al  = B_xx s_x E_y + B_yy E_x s_y + B_xy d_x d_y,
+//   gam = B_xz d_x E_y + B_yz E_x d_y,  bet = B_zz Exy + W_x W_y M_zz,
+//   A   = W_x W_y [p* + 3/2 (c_x F_x + c_y F_y) + 9/2 (M_xx (c_x^2 - 1/3)
+//         + M_yy (c_y^2 - 1/3)) + 9 M_xy c_x c_y],
+//   Bf  = W_x W_y [3/2 F_z + 9 (M_xz c_x + M_yz c_y)],   M = (u F + F u)/2,
+// and Q1 = P + al + A, Q2 = Exy + al, R = 3/2 u_z^2 Q2 + 3/2 bet + 3 u_z gam:
+//   f(c_z = 0)  = 2 (Q1 - R),
+//   f(c_z = +-1) = Q1 / 2 + R +- (3/2 u_z Q2 + 3/2 gam + Bf / 2).
+// Every intermediate is a deviation of order u, B or F (the rest weights
+// cancel in P), so FP32 keeps its precision relative to the flow.
+template <typename C>
+__device__ __forceinline__ void source_pops_full(const C m[10], C Fx, C Fy, C Fz, C omega,
+                                                 C g[27]) {
+  using L = Lat<27>;
+  const C h = C(0.5);
+  const C om1 = C(1) - omega;
+  const C ux = m[1], uy = m[2], uz = m[3];
+  // (1 - omega) a2neq
+  const C Bxx = om1 * (m[4] - ux * ux), Byy = om1 * (m[5] - uy * uy);
+  const C Bzz = om1 * (m[6] - uz * uz), Bxy = om1 * (m[7] - ux * uy);
+  const C Bxz = om1 * (m[8] - ux * uz), Byz = om1 * (m[9] - uy * uz);
+  // Hermite coefficient of the Guo term, (u F + F u) / 2
+  const C Mxx = ux * Fx, Myy = uy * Fy, Mzz = uz * Fz;
+  const C Mxy = h * (ux * Fy + uy * Fx), Mxz = h * (ux * Fz + uz * Fx);
+  const C Myz = h * (uy * Fz + uz * Fy);
+  constexpr C W[3] = {C(0.5), C(2), C(0.5)};
+  constexpr C sv[3] = {C(1.5), C(-3), C(1.5)};
+  // per-axis factors of x and y, and their products with the column terms
+  C ex[3], Ex[3], dx[3], ey[3], Ey[3], dy[3];
+  {
+    const C uxx = ux * ux, uyy = uy * uy;
+    ex[0] = C(1.5) * (uxx - ux), ex[1] = C(-3) * uxx, ex[2] = C(1.5) * (uxx + ux);
+    ey[0] = C(1.5) * (uyy - uy), ey[1] = C(-3) * uyy, ey[2] = C(1.5) * (uyy + uy);
+    dx[0] = C(3) * ux - C(1.5), dx[1] = C(-6) * ux, dx[2] = C(3) * ux + C(1.5);
+    dy[0] = C(3) * uy - C(1.5), dy[1] = C(-6) * uy, dy[2] = C(3) * uy + C(1.5);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Ex[c] = W[c] + ex[c], Ey[c] = W[c] + ey[c];
+  }
+  // p* and the x, y parts of the force term: 3/2 c F_a + 9/2 M_aa (c^2 - 1/3)
+  const C fx[3] = {C(-1.5) * Fx + C(3) * Mxx, C(-1.5) * Mxx, C(1.5) * Fx + C(3) * Mxx};
+  const C fy[3] = {C(-1.5) * Fy + C(3) * Myy, C(-1.5) * Myy, C(1.5) * Fy + C(3) * Myy};
+  const C h2 = C(1.5) * uz * uz, h1 = C(1.5) * uz;
+  static_for<9>([&](auto J) {
+    constexpr int cx = decltype(J)::value / 3, cy = decltype(J)::value % 3;
+    constexpr C WW = W[cx] * W[cy];
+    constexpr C sx = (cx - 1) * C(9), sy = (cy - 1) * C(9), sxy = (cx - 1) * (cy - 1) * C(9);
+    const C Exy = Ex[cx] * Ey[cy];
+    const C P = ex[cx] * Ey[cy] + W[cx] * ey[cy];
+    const C al = Bxx * sv[cx] * Ey[cy] + Byy * sv[cy] * Ex[cx] + Bxy * dx[cx] * dy[cy];
+    const C gam = Bxz * dx[cx] * Ey[cy] + Byz * dy[cy] * Ex[cx];
+    const C bet = Bzz * Exy + WW * Mzz;
+    const C A = WW * (m[0] + fx[cx] + fy[cy] + sxy * Mxy);
+    const C Bf = WW * (C(1.5) * Fz + sx * Mxz + sy * Myz);
+    const C Q1 = P + al + A;
+    const C Q2 = Exy + al;
+    const C R = h2 * Q2 + C(1.5) * bet + C(2) * h1 * gam;
+    const C even = h * Q1 + R;
+    const C odd = h1 * Q2 + C(1.5) * gam + h * Bf;
+    g[L::index(cx - 1, cy - 1, 0)] = C(2) * (Q1 - R);
+    g[L::index(cx - 1, cy - 1, 1)] = even + odd;
+    g[L::index(cx - 1, cy - 1, -1)] = even - odd;
+  });
 }
 
 // Steps 4-5 at one destination site: the running projections (units of 1/D)
@@ -79,10 +167,12 @@ __device__ __forceinline__ void finalize(const Sums<C>& S, C Fx, C Fy, C Fz, C o
 // VAR: density and viscosity follow the phase field (section 2): the source
 // relaxes with omega(phi(t)) and applies F(t) / rho(phi(t)), the correction
 // applies F(t+1) / rho(phi(t+1)).
-template <int Q_, int ST, bool FFIELD, bool FNEXT = false, bool VAR = false>
+// FULL: D3Q27h, the source populations over the complete Hermite basis.
+template <int Q_, int ST, bool FFIELD, bool FNEXT = false, bool VAR = false, bool FULL = false>
 struct Forward {
   static_assert(FFIELD || !FNEXT, "a time-dependent force is a force field");
   static_assert(FNEXT || !VAR, "variable properties come with the two-component force");
+  static_assert(!FULL || Q_ == 27, "the complete Hermite basis is the D3Q27 one");
   static constexpr int Q = Q_;
   using S = Storage<ST>;
   using C = typename S::C;
@@ -187,7 +277,10 @@ struct Forward {
           c.F[k] = F[k];
       }
     }
-    source_pops<Q, C>(m, F[0], F[1], F[2], omega, g);
+    if constexpr (FULL)
+      source_pops_full<C>(m, F[0], F[1], F[2], omega, g);
+    else
+      source_pops<Q, C>(m, F[0], F[1], F[2], omega, g);
   }
 
   template <int NS>
@@ -219,41 +312,55 @@ struct Forward {
   }
 };
 
-template <int Q, int ST, int TY, bool WALLY, bool FFIELD>
+template <int Q, int ST, int TY, bool WALLY, bool FFIELD, bool FULL = false>
 hipError_t launch_step_t(const StepArgs& a, hipStream_t stream) {
   if constexpr (FFIELD && TY <= 8) {
     // a force that changes every step (two-component flow), with or without
     // density and viscosity contrast
     if (a.Fnext && a.phi_src)
-      return launch_march<Forward<Q, ST, true, true, true>, TY, WALLY>(a, stream);
-    if (a.Fnext) return launch_march<Forward<Q, ST, true, true>, TY, WALLY>(a, stream);
+      return launch_march<Forward<Q, ST, true, true, true, FULL>, TY, WALLY>(a, stream);
+    if (a.Fnext) return launch_march<Forward<Q, ST, true, true, false, FULL>, TY, WALLY>(a, stream);
   }
   if (a.Fnext) return hipErrorInvalidValue;
-  return launch_march<Forward<Q, ST, FFIELD>, TY, WALLY>(a, stream);
+  return launch_march<Forward<Q, ST, FFIELD, false, false, FULL>, TY, WALLY>(a, stream);
 }
 
-// all (Q, tile rows, walls, force field) variants of one storage type
-template <int ST>
-hipError_t launch_step_storage(int Q, int tile_rows, bool walls_y, bool ffield, const StepArgs& a,
-                               hipStream_t s) {
-#define LBF_CASE(QQ, TYY)                                                          \
-  if (Q == QQ && tile_rows == TYY) {                                              \
+// all (lattice, tile rows, walls, force field) variants of one storage type
+// for the second-order sets (lattice 19 or 27), and for D3Q27h (tile rows 4,
+// 6 and 8; compiled in translation units of their own)
+#define LBF_CASE(QQ, FULL, TYY)                                                   \
+  if (tile_rows == TYY) {                                                         \
     if (walls_y)                                                                  \
-      return ffield ? launch_step_t<QQ, ST, TYY, true, true>(a, s)                \
-                    : launch_step_t<QQ, ST, TYY, true, false>(a, s);              \
-    return ffield ? launch_step_t<QQ, ST, TYY, false, true>(a, s)                 \
-                  : launch_step_t<QQ, ST, TYY, false, false>(a, s);               \
+      return ffield ? launch_step_t<QQ, ST, TYY, true, true, FULL>(a, s)          \
+                    : launch_step_t<QQ, ST, TYY, true, false, FULL>(a, s);        \
+    return ffield ? launch_step_t<QQ, ST, TYY, false, true, FULL>(a, s)           \
+                  : launch_step_t<QQ, ST, TYY, false, false, FULL>(a, s);         \
   }
-  LBF_CASE(19, 4)
-  LBF_CASE(19, 6)
-  LBF_CASE(19, 8)
-  LBF_CASE(19, 14)
-  LBF_CASE(27, 4)
-  LBF_CASE(27, 6)
-  LBF_CASE(27, 8)
-  LBF_CASE(27, 14)
-#undef LBF_CASE
+template <int ST>
+hipError_t launch_step_storage(int lattice, int tile_rows, bool walls_y, bool ffield,
+                               const StepArgs& a, hipStream_t s) {
+  if (lattice == 19) {
+    LBF_CASE(19, false, 4)
+    LBF_CASE(19, false, 6)
+    LBF_CASE(19, false, 8)
+    LBF_CASE(19, false, 14)
+  } else if (lattice == 27) {
+    LBF_CASE(27, false, 4)
+    LBF_CASE(27, false, 6)
+    LBF_CASE(27, false, 8)
+    LBF_CASE(27, false, 14)
+  }
   return hipErrorInvalidValue;
 }
+
+template <int ST>
+hipError_t launch_step_storage_full(int tile_rows, bool walls_y, bool ffield, const StepArgs& a,
+                                    hipStream_t s) {
+  LBF_CASE(27, true, 4)
+  LBF_CASE(27, true, 6)
+  LBF_CASE(27, true, 8)
+  return hipErrorInvalidValue;
+}
+#undef LBF_CASE
 
 }  // namespace lbf

@@ -14,7 +14,8 @@ MOMENT_NAMES = ("p*", "ux", "uy", "uz", "a2xx", "a2yy", "a2zz", "a2xy", "a2xz", 
 class Solver:
     """One moment-represented LBM lattice on one GPU.
 
-    shape = (nx, ny, nz); storage in {"f64", "f32", "f16s", "bf16s"};
+    shape = (nx, ny, nz); lattice in {19, 27, "27h"} ("27h": the D3Q27 set
+    with the complete Hermite basis); storage in {"f64", "f32", "f16s", "bf16s"};
     bc = per-axis 0 (periodic) / 1 (walls, y only); force = uniform body force.
     The two flip/flop moment buffers are torch allocations on `device`, the
     launches go to torch's current stream of that device.

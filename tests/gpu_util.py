@@ -40,6 +40,11 @@ def oracle_run(shape, tau, m0, steps, lattice=19, bc=(0, 0, 0), force=None):
 _CACHE = {}
 
 
+def lattice_number(Q):
+    """An integer for seeds and labels: 19, 27, or 270 for "27h"."""
+    return 270 if Q == "27h" else int(Q)
+
+
 def solenoidal_oracle_1000(Q, n=64, tau=0.6):
     """Oracle moments after 1000 steps of the n^3 solenoidal workload (cached:
     several storage types compare against the same reference)."""

@@ -251,11 +251,15 @@ def test_autograd_function_matches_direct_call():
 
 
 def test_adjoint_argument_errors():
-    """16-bit storage has no adjoint; bad step counts are rejected on the
-    host before any device work."""
+    """16-bit storage and the full-basis D3Q27h set have no adjoint; bad
+    step counts are rejected on the host before any device work."""
     import torch
     from paper_2609_09160_amd import LbfastError, Solver
     s = Solver((8, 8, 8), 0.8, storage="f16s", scale=[2.0 ** -10] * 10)
+    with pytest.raises(LbfastError, match="UNSUPPORTED"):
+        s.forward_checkpointed(4, 2)
+    s.close()
+    s = Solver((8, 8, 8), 0.8, lattice="27h", storage="f32")
     with pytest.raises(LbfastError, match="UNSUPPORTED"):
         s.forward_checkpointed(4, 2)
     s.close()

@@ -7,7 +7,8 @@ import pytest
 
 from paper_2609_09160_amd import inputs
 
-from gpu_util import gpu_run, oracle_run, oracle_site_update, say, solenoidal_oracle_1000, u_rel_l2
+from gpu_util import (gpu_run, lattice_number, oracle_run, oracle_site_update, say,
+                      solenoidal_oracle_1000, u_rel_l2)
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -19,7 +20,7 @@ def _cuda():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
 
 
-@pytest.mark.parametrize("Q", [19, 27])
+@pytest.mark.parametrize("Q", [19, 27, "27h"])
 @pytest.mark.parametrize("storage,bound", [("f16s", 1e-3), ("bf16s", 1e-1)])
 def test_16bit_storage_accuracy(Q, storage, bound):
     """16-bit scaled moment storage (FP32 arithmetic), 64^3 solenoidal workload,
@@ -37,7 +38,7 @@ def test_16bit_storage_accuracy(Q, storage, bound):
     assert e <= bound
 
 
-@pytest.mark.parametrize("Q", [19, 27])
+@pytest.mark.parametrize("Q", [19, 27, "27h"])
 def test_sampled_sites_512(Q):
     """Full size, bench launch configuration: one FP32 step of the 512^3
     workload; 48 sampled sites (tile and domain edges included) against the
@@ -53,7 +54,7 @@ def test_sampled_sites_512(Q):
     s.step(1)
     out = s.moments(dtype=torch.float32)
     s.close()
-    rng = np.random.Generator(np.random.PCG64(512 + Q))
+    rng = np.random.Generator(np.random.PCG64(512 + lattice_number(Q)))
     pts = [(0, 0, 0), (511, 511, 511), (63, 7, 0), (64, 8, 511), (127, 255, 256), (0, 511, 1)]
     pts += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(42)]
     err = 0.0

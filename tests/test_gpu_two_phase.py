@@ -12,7 +12,7 @@ FP64 run (below)."""
 import numpy as np
 import pytest
 
-from gpu_util import group_rel_err, say
+from gpu_util import group_rel_err, lattice_number, say
 
 pytestmark = pytest.mark.gpu
 
@@ -76,13 +76,13 @@ def _droplet_state(shape, R, seed, noise=True):
 
 
 @pytest.mark.parametrize("sites", [1, 2])
-@pytest.mark.parametrize("Q", [19, 27])
+@pytest.mark.parametrize("Q", [19, 27, "27h"])
 def test_two_phase_parity_fp64(Q, sites):
     """70 x 21 x 18 (ragged), off-centre droplet R = 6 with a perturbed flow
     and a uniform body force, 30 steps, FP64, one or two x-sites per lane:
     moments and phi element-wise."""
     shape = (70, 21, 18)
-    m0, _ = _droplet_state(shape, 6, seed=Q)
+    m0, _ = _droplet_state(shape, 6, seed=lattice_number(Q))
     from oracle import two_phase as T
     phi0 = T.droplet(shape, 6, W, center=(30.3, 10.1, 8.7))
     Fb = (2e-6, -1e-6, 5e-7)
@@ -184,7 +184,7 @@ def test_laplace_256_16bit(storage, bar):
 
 @pytest.mark.parametrize("sites", [1, 2])
 @pytest.mark.parametrize("walls", [False, True])
-@pytest.mark.parametrize("Q", [19, 27])
+@pytest.mark.parametrize("Q", [19, 27, "27h"])
 def test_contrast_parity_fp64(Q, walls, sites):
     """Density and viscosity contrast (rho 0.5 / 1.5, nu 0.05 / 0.4), body
     acceleration, periodic or y walls, 70 x 21 x 18, off-centre droplet with
@@ -192,7 +192,7 @@ def test_contrast_parity_fp64(Q, walls, sites):
     the two-component oracle."""
     from oracle import two_phase as T
     shape = (70, 21, 18)
-    m0, _ = _droplet_state(shape, 6, seed=Q + 3)
+    m0, _ = _droplet_state(shape, 6, seed=lattice_number(Q) + 3)
     phi0 = T.droplet(shape, 6, W, center=(30.3, 10.1, 8.7))
     g = (2e-6, -1e-6, 5e-7)
     bc = (0, 1 if walls else 0, 0)

@@ -71,6 +71,7 @@ def _create(lib, p, bufs=(None, None)):
     (lambda p: setattr(p, "tau", 0.5), _lib.LBF_E_ARG, "tau"),
     (lambda p: setattr(p, "tau", float("nan")), _lib.LBF_E_ARG, "tau"),
     (lambda p: setattr(p, "lattice", 15), _lib.LBF_E_ARG, "lattice"),
+    (lambda p: setattr(p, "lattice", 28), _lib.LBF_E_ARG, "lattice"),
     (lambda p: setattr(p, "storage", 7), _lib.LBF_E_ARG, "storage"),
     (lambda p: setattr(p, "nx", 0), _lib.LBF_E_ARG, "extent"),
     (lambda p: setattr(p, "struct_size", 8), _lib.LBF_E_ARG, "struct_size"),
@@ -125,9 +126,13 @@ def test_last_error_is_per_thread(lib):
     assert "tau" in main_msg and other["msg"] == ""
 
 
-def test_valid_params_without_gpu_report_device_error(lib):
+@pytest.mark.parametrize("lattice", [19, 27, "27h"])
+def test_valid_params_without_gpu_report_device_error(lib, lattice):
     import torch
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
-    rc, msg = _create(lib, _lib.make_params((8, 8, 8), 0.8))
+    p = _lib.make_params((8, 8, 8), 0.8, lattice=lattice)
+    assert p.lattice == {19: 19, 27: 27, "27h": 270}[lattice]
+    assert lib.lbfast_buffer_bytes(ctypes.byref(p)) == 10 * 8 ** 3 * 4
+    rc, msg = _create(lib, p)
     assert rc == _lib.LBF_E_DEVICE and msg
