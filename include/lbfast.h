@@ -221,7 +221,12 @@ int lbfast_get_phase(lbfast_t h, void* phi, int dtype, int on_device);
  * backwards: each is recomputed from its checkpoint into work_dev (k + 2
  * buffers of lbfast_buffer_bytes(p): the k recomputed states and two
  * adjoint buffers; see lbfast_adjoint_work_bytes) and swept with one adjoint
- * step per time step.  The force (field or uniform), tau, lattice and
+ * step per time step.  With every = 1 every state but the final one is a
+ * checkpoint: the forward steps write straight into their slots (no copies)
+ * and the adjoint reads each step's two states from ckpt_dev, recomputing
+ * only the last step; the backward pass then costs one adjoint step per time
+ * step, for nsteps buffers of checkpoint memory (500 steps of a 192^3 FP32
+ * lattice: 142 GB).  The force (field or uniform), tau, lattice and
  * boundaries in use must be those of the forward run.
  *
  * Arrays (device, compute type: double for F64, float for F32 storage):

@@ -748,10 +748,24 @@ int lbfast_forward_checkpointed(lbfast_t h, int64_t nsteps, int64_t every, void*
   const size_t bytes = lbfast_buffer_bytes(&h->p);
   lbf::StepArgs a;
   if (int rc = step_args(h, &a)) return rc;
+  char* ck = static_cast<char*>(ckpt_dev);
+  if (every == 1 && nsteps > 0) {
+    // every state is kept: each step writes straight into the next slot, and
+    // only the last one (the final state, which has no slot) into the buffer
+    hipError_t e = hipMemcpyAsync(ck, h->buf[h->cur], bytes, hipMemcpyDeviceToDevice, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
+    for (int64_t t = 0; t < nsteps; ++t) {
+      a.src = ck + t * bytes;
+      a.dst = (t + 1 < nsteps) ? static_cast<void*>(ck + (t + 1) * bytes) : h->buf[h->cur ^ 1];
+      if (int rc = launch_forward(h, a)) return rc;
+    }
+    h->cur ^= 1;
+    return LBF_OK;
+  }
   for (int64_t t = 0; t < nsteps; ++t) {
     if (t % every == 0) {
-      hipError_t e = hipMemcpyAsync(static_cast<char*>(ckpt_dev) + (t / every) * bytes,
-                                    h->buf[h->cur], bytes, hipMemcpyDeviceToDevice, h->stream);
+      hipError_t e = hipMemcpyAsync(ck + (t / every) * bytes, h->buf[h->cur], bytes,
+                                    hipMemcpyDeviceToDevice, h->stream);
       if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
     }
     a.src = h->buf[h->cur];
@@ -815,11 +829,16 @@ int lbfast_adjoint(lbfast_t h, int64_t nsteps, int64_t every, const void* ckpt_d
   const bool walls_y = h->p.bc[1] == LBF_WALLS;
   for (int64_t seg = nseg - 1; seg >= 0; --seg) {
     const int64_t len = std::min(every, nsteps - seg * every);
+    char* ck = static_cast<char*>(const_cast<void*>(ckpt_dev));
+    // with every == 1 all states but the final one are checkpoints, and only
+    // the last segment recomputes its end state
+    const bool stored = every == 1 && seg + 1 < nseg;
     auto state = [&](int64_t j) -> void* {  // state at t = seg*every + j
-      return j == 0 ? static_cast<void*>(static_cast<char*>(const_cast<void*>(ckpt_dev)) + seg * bytes)
+      if (j == 0) return ck + seg * bytes;
+      return stored ? static_cast<void*>(ck + (seg + 1) * bytes)
                     : static_cast<void*>(work + (j - 1) * bytes);
     };
-    for (int64_t j = 0; j < len; ++j) {  // recompute the segment
+    for (int64_t j = 0; j < len && !stored; ++j) {  // recompute the segment
       fa.src = state(j);
       fa.dst = state(j + 1);
       if (int rc = launch_forward(h, fa)) return rc;

@@ -120,7 +120,7 @@ def _golden(name):
     return out
 
 
-@pytest.mark.parametrize("Q", [19, 27])
+@pytest.mark.parametrize("Q", [19, 27, "27h"])
 def test_taylor_green_512(Q):
     """The paper's Taylor-Green validation at its own size: 512^3, nu = 0.04074,
     U0 = 0.04, FP32.  A linear fit of log(E/E0) over the first 4000 steps gives
@@ -163,7 +163,7 @@ def test_taylor_green_512(Q):
     s.close()
     ts, E = np.array(ts), np.array(E)
     k2 = (2 * np.pi / n) ** 2
-    paper = gd["nu_fit_D3Q19" if Q == 19 else "nu_fit_D3Q27"]
+    paper = gd[{19: "nu_fit_D3Q19", 27: "nu_fit_D3Q27", "27h": "nu_fit_D3Q27h"}[Q]]
     fits = {}
     for T in (250, 500, 1000, 2000):
         sel = ts <= T
