@@ -8,7 +8,9 @@
 The forward pass runs nsteps fused steps with the per-site force field F
 (static in time), saving the state every `every` steps; the backward pass
 recomputes each segment from its checkpoint and sweeps it with the adjoint
-step, all on the GPU.  Storage F64 or F32 (the compute dtype of F and of the
+step, all on the GPU.  every=1 keeps every state (nsteps state buffers of
+HBM) and the backward pass then recomputes nothing: the fastest choice when
+the memory is there.  Storage F64 or F32 (the compute dtype of F and of the
 gradients).  The paper itself does not treat differentiation.
 """
 import torch
