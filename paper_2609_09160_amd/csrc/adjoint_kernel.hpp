@@ -106,7 +106,7 @@ struct Adjoint {
     }
   }
 
-  template <bool OWN>
+  template <bool OWN, int SEL>
   static __device__ __forceinline__ void source(const StepArgs& a, const Raw<OWN>& r, C g[Q],
                                                 Carry& c) {
     const C h = C(0.5);
@@ -119,7 +119,7 @@ struct Adjoint {
     const C s1y = l[2] + l[5] * F[1] + h * (l[7] * F[0] + l[9] * F[2]);
     const C s1z = l[3] + l[6] * F[2] + h * (l[8] * F[0] + l[9] * F[1]);
     const C A = l[0] - div_by<3>(l[4] + l[5] + l[6]);
-    expand<Q, C>(A, l[4], l[5], l[6], l[7], l[8], l[9], -s1x, -s1y, -s1z, g);
+    expand<Q, C, SEL>(A, l[4], l[5], l[6], l[7], l[8], l[9], -s1x, -s1y, -s1z, g);
     if constexpr (OWN) {
       const C* un = r.x;  // u(t+1) at this site
 #pragma unroll

@@ -136,16 +136,14 @@ constexpr size_t kLdsLimit = 160 * 1024;
 // where nx allows it (even, at least one 128-wide tile), 8-row tiles (FP64:
 // 4 rows with two sites per lane, 6 with one) or the tallest that fits the
 // LDS; z-chunks only when the column tiles alone give too few workgroups.
-// D3Q27h is bound by its arithmetic: one site per lane (8 rows, FP64 6) except
-// with 16-bit storage, where two sites per lane measured faster.
+// D3Q27h in FP64 keeps one site per lane (6 rows): two spill registers there.
 void default_launch(lbfast_ctx* h) {
   // two sites per lane unless 128-wide tiles would leave more of the last
   // tile empty than 64-wide ones
   const int64_t waste1 = ceil_div(h->p.nx, 64) * 64 - h->p.nx;
   const int64_t waste2 = ceil_div(h->p.nx, 128) * 128 - h->p.nx;
   h->lane_sites = (h->p.nx % 2 == 0 && h->p.nx >= 128 && waste2 <= waste1) ? 2 : 1;
-  const bool bits16 = h->p.storage == LBF_F16S || h->p.storage == LBF_BF16S;
-  if (h->p.lattice == LBF_D3Q27H && !bits16) h->lane_sites = 1;
+  if (h->p.lattice == LBF_D3Q27H && h->p.storage == LBF_F64) h->lane_sites = 1;
   h->tile_rows = 4;
   const bool f64 = h->p.storage == LBF_F64;
   for (int ty : {f64 ? (h->lane_sites == 2 ? 4 : 6) : 8, 6, 4})

@@ -18,7 +18,9 @@
 //   P::Carry                  per-site data a source hands to its own
 //                             destination one plane later
 //   P::fetch<OWN, S>(a, pb, off, plane_bytes, raw[S])   S consecutive sites
-//   P::source<OWN>(a, raw, g[Q], carry)   g in units of 1/D (D = Lat<Q>::D)
+//   P::source<OWN, SEL>(a, raw, g[Q], carry)   g in units of 1/D (D =
+//                             Lat<Q>::D); halo sites (SEL != kSelAll) only
+//                             need the directions that enter the tile
 //   P::finish<S>(a, sums[S], carry[S], pb, off, plane_bytes)   store S
 //                             consecutive destinations
 //
@@ -50,16 +52,32 @@
 
 namespace lbf {
 
+// Which values a source site has to produce: all of them (sites the
+// workgroup owns), or only those that enter the tile from a halo site: c_y =
+// +1 from the halo row below, c_y = -1 from the row above, c_x = +1 from the
+// halo column on the left, c_x = -1 from the one on the right.
+enum { kSelAll = 0, kSelUp = 1, kSelDown = 2, kSelRight = 3, kSelLeft = 4 };
+template <int SEL>
+constexpr bool selected(int cx, int cy) {
+  return SEL == kSelAll || (SEL == kSelUp && cy == 1) || (SEL == kSelDown && cy == -1) ||
+         (SEL == kSelRight && cx == 1) || (SEL == kSelLeft && cx == -1);
+}
+template <int Q, int SEL>
+constexpr bool selected_dir(int i) {
+  return selected<SEL>(Lat<Q>::cx(i), Lat<Q>::cy(i));
+}
+
 // Values leaving one site along each direction, in units of 1/D, from the
 // coefficients of the expansion
 //   g_i = k_i [A + sum_a D_a c_ia^2 + sum_{a<b} O_ab c_ia c_ib + sum_a V_a c_ia],
-// k_i = D w_i.
-template <int Q, typename C>
+// k_i = D w_i (only the directions SEL selects are written).
+template <int Q, typename C, int SEL = kSelAll>
 __device__ __forceinline__ void expand(C A, C Dx, C Dy, C Dz, C Oxy, C Oxz, C Oyz, C Vx, C Vy,
                                        C Vz, C g[Q]) {
   using L = Lat<Q>;
   static_for<Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
+    if constexpr (!selected_dir<Q, SEL>(i)) return;
     constexpr int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
     C v = A;
     if constexpr (cx != 0) v += Dx;
@@ -189,12 +207,14 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
   auto fetch_col = [&](const int zs, const uint32_t off, RawHalo (&r)[1]) __attribute__((always_inline)) {
     P::template fetch<false, 1>(a, static_cast<int64_t>(zwrap(zs)) * plane, off, plane_bytes, r);
   };
-  auto stage = [&](const C g[Q], const int row, const int col) __attribute__((always_inline)) {
+  auto stage = [&](auto SEL, const C g[Q], const int row, const int col)
+                   __attribute__((always_inline)) {
     static_for<NP>([&](auto I) {
       constexpr int i = decltype(I)::value;
-      lds[i][row][col] = g[i];
+      if constexpr (selected_dir<Q, decltype(SEL)::value>(i)) lds[i][row][col] = g[i];
     });
   };
+  using SelAll = std::integral_constant<int, kSelAll>;
   // value i arriving at the destination of own site s from the LDS plane; on
   // a wall row the ones that would come from beyond the wall are dropped here
   // and replaced by the reflections added in body_interior
@@ -225,8 +245,8 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
     static_for<S>([&](auto SI) {
       constexpr int s = decltype(SI)::value;
       C g[Q];
-      P::template source<true>(a, rc[s], g, cs[s]);
-      stage(g, wv, S * lane + s + 1);
+      P::template source<true, kSelAll>(a, rc[s], g, cs[s]);
+      stage(SelAll{}, g, wv, S * lane + s + 1);
       gc[s][0] = g[L::kRest];
       gc[s][1] = g[L::kUp];
       gc[s][2] = g[L::kDown];
@@ -306,39 +326,44 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
   // interior waves (evaluate, then pull + project), the column site of plane
   // zs+1 is evaluated during phase 2 of plane zs into colbuf, and copied into
   // the plane's column slots during phase 1 of zs+1 (same lane writes and
-  // reads colbuf, so it needs no barrier of its own).
+  // reads colbuf, so it needs no barrier of its own).  A halo site evaluates
+  // only the values that enter the tile (RS for the row, CS for the column:
+  // wave 0 holds the row below and the left column, wave R-1 the row above and
+  // the right column).
   const int hwave = (wv == 0) ? 0 : 1;
   // lanes without an x-halo site fetch at the plane end: zeros, no fault
   const uint32_t off_hf = do_halo ? off_h : plane_bytes;
-  auto col_to_buf = [&](const RawHalo& r) __attribute__((always_inline)) {
+  auto col_to_buf = [&](auto CS, const RawHalo& r) __attribute__((always_inline)) {
+    constexpr int cs_sel = decltype(CS)::value;
     C g[Q];
     Carry cs;
-    P::template source<false>(a, r, g, cs);
+    P::template source<false, cs_sel>(a, r, g, cs);
     if (do_halo)
       static_for<NP>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        colbuf[i][hwave][lane] = g[i];
+        if constexpr (selected_dir<Q, cs_sel>(i)) colbuf[i][hwave][lane] = g[i];
       });
   };
   // rc: this plane's row sites, rn: receives plane zs+ahead; hc: the column
   // site of plane zs+1, refilled after use with plane zs+1+U
-  auto body_halo = [&](const int zs, RawHalo (&rc)[S], RawHalo (&rn)[S], RawHalo (&hc)[1],
-                       const int ahead) __attribute__((always_inline)) {
+  auto body_halo = [&](auto RS, auto CS, const int zs, RawHalo (&rc)[S], RawHalo (&rn)[S],
+                       RawHalo (&hc)[1], const int ahead) __attribute__((always_inline)) {
+    constexpr int rs_sel = decltype(RS)::value, cs_sel = decltype(CS)::value;
     fetch_row(zs + ahead, off_s, rn);
     if (do_halo)
       static_for<NP>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        lds[i][lane][hcol] = colbuf[i][hwave][lane];
+        if constexpr (selected_dir<Q, cs_sel>(i)) lds[i][lane][hcol] = colbuf[i][hwave][lane];
       });
     static_for<S>([&](auto SI) {
       constexpr int s = decltype(SI)::value;
       C g[Q];
       Carry cs;
-      P::template source<false>(a, rc[s], g, cs);
-      stage(g, wv, S * lane + s + 1);
+      P::template source<false, rs_sel>(a, rc[s], g, cs);
+      stage(RS, g, wv, S * lane + s + 1);
     });
     __syncthreads();
-    col_to_buf(hc[0]);
+    col_to_buf(CS, hc[0]);
     fetch_col(zs + 1 + (ahead + 1), off_hf, hc);
     __syncthreads();
   };
@@ -375,22 +400,30 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
       });
     }
   } else {
-    RawHalo rr[U][S], hh[U][1];
-    {
-      RawHalo first[1];
-      fetch_col(z0 - 1, off_hf, first);
-      col_to_buf(first[0]);  // columns of the first source plane
-    }
-    static_for<U>([&](auto J) { fetch_col(z0 + J, off_hf, hh[J]); });
-    static_for<PF>([&](auto J) { fetch_row(z0 - 1 + J, off_s, rr[J]); });
+    auto halo_loop = [&](auto RS, auto CS) __attribute__((always_inline)) {
+      RawHalo rr[U][S], hh[U][1];
+      {
+        RawHalo first[1];
+        fetch_col(z0 - 1, off_hf, first);
+        col_to_buf(CS, first[0]);  // columns of the first source plane
+      }
+      static_for<U>([&](auto J) { fetch_col(z0 + J, off_hf, hh[J]); });
+      static_for<PF>([&](auto J) { fetch_row(z0 - 1 + J, off_s, rr[J]); });
 #pragma unroll 1
-    for (int t = 0; t < trips; ++t) {
-      const int zb = z0 - 1 + t * U;
-      static_for<U>([&](auto K) {
-        constexpr int k = decltype(K)::value;
-        body_halo(zb + k, rr[k], rr[(k + PF) % U], hh[k], PF);
-      });
-    }
+      for (int t = 0; t < trips; ++t) {
+        const int zb = z0 - 1 + t * U;
+        static_for<U>([&](auto K) {
+          constexpr int k = decltype(K)::value;
+          body_halo(RS, CS, zb + k, rr[k], rr[(k + PF) % U], hh[k], PF);
+        });
+      }
+    };
+    // uniform per wave: each halo wave runs one of the two loops, with the
+    // same trips and barriers
+    if (wv == 0)
+      halo_loop(std::integral_constant<int, kSelUp>{}, std::integral_constant<int, kSelRight>{});
+    else
+      halo_loop(std::integral_constant<int, kSelDown>{}, std::integral_constant<int, kSelLeft>{});
   }
 }
 

@@ -31,7 +31,7 @@ namespace lbf {
 // Steps 1-2 at one source site: post-collision coefficients and the
 // reconstructed populations, kept in units of 1/D: g[i] = D f_i(y) with
 // D f_i = k_i [P0 - 1.5 tr P2 + 3 c.P1 + 4.5 c c : P2], k_i = D w_i.
-template <int Q, typename C>
+template <int Q, typename C, int SEL = kSelAll>
 __device__ __forceinline__ void source_pops(const C m[10], C Fx, C Fy, C Fz, C omega, C g[Q]) {
   const C h = C(0.5);
   const C om1 = C(1) - omega;
@@ -47,7 +47,7 @@ __device__ __forceinline__ void source_pops(const C m[10], C Fx, C Fy, C Fz, C o
   const C Vx = C(3) * (ux + h * Fx), Vy = C(3) * (uy + h * Fy), Vz = C(3) * (uz + h * Fz);
   const C Dx = C(4.5) * P2xx, Dy = C(4.5) * P2yy, Dz = C(4.5) * P2zz;
   const C Oxy = C(9) * P2xy, Oxz = C(9) * P2xz, Oyz = C(9) * P2yz;
-  expand<Q, C>(A, Dx, Dy, Dz, Oxy, Oxz, Oyz, Vx, Vy, Vz, g);
+  expand<Q, C, SEL>(A, Dx, Dy, Dz, Oxy, Oxz, Oyz, Vx, Vy, Vz, g);
 }
 
 // D3Q27h, steps 1-2 over the complete Hermite basis of D3Q27 (section 2,
@@ -82,7 +82,7 @@ __device__ __forceinline__ void source_pops(const C m[10], C Fx, C Fy, C Fz, C o
 //   f(c_z = +-1) = Q1 / 2 + R +- (3/2 u_z Q2 + 3/2 gam + Bf / 2).
 // Every intermediate is a deviation of order u, B or F (the rest weights
 // cancel in P), so FP32 keeps its precision relative to the flow.
-template <typename C>
+template <typename C, int SEL = kSelAll>
 __device__ __forceinline__ void source_pops_full(const C m[10], C Fx, C Fy, C Fz, C omega,
                                                  C g[27]) {
   using L = Lat<27>;
@@ -116,6 +116,7 @@ __device__ __forceinline__ void source_pops_full(const C m[10], C Fx, C Fy, C Fz
   const C h2 = C(1.5) * uz * uz, h1 = C(1.5) * uz;
   static_for<9>([&](auto J) {
     constexpr int cx = decltype(J)::value / 3, cy = decltype(J)::value % 3;
+    if constexpr (!selected<SEL>(cx - 1, cy - 1)) return;
     constexpr C WW = W[cx] * W[cy];
     constexpr C sx = (cx - 1) * C(9), sy = (cy - 1) * C(9), sxy = (cx - 1) * (cy - 1) * C(9);
     const C Exy = Ex[cx] * Ey[cy];
@@ -239,7 +240,7 @@ struct Forward {
     }
   }
 
-  template <bool OWN>
+  template <bool OWN, int SEL>
   static __device__ __forceinline__ void source(const StepArgs& a, const Raw<OWN>& r, C g[Q],
                                                 Carry& c) {
     C m[10];
@@ -278,9 +279,9 @@ struct Forward {
       }
     }
     if constexpr (FULL)
-      source_pops_full<C>(m, F[0], F[1], F[2], omega, g);
+      source_pops_full<C, SEL>(m, F[0], F[1], F[2], omega, g);
     else
-      source_pops<Q, C>(m, F[0], F[1], F[2], omega, g);
+      source_pops<Q, C, SEL>(m, F[0], F[1], F[2], omega, g);
   }
 
   template <int NS>
