@@ -126,9 +126,17 @@ __global__ void __launch_bounds__(kPhaseThreads) flux_kernel(
 }
 
 // phi' = phi - div(V) + D lap(phi).  A workgroup owns a 64 x kUpdRows column
-// tile and a chunk of z-planes and marches through z, keeping three planes
-// of records (with a one-site halo) in LDS: each record is read from memory
-// about once (plus halo) instead of 27 times.
+// tile and a chunk of z-planes and marches through z.  One plane of records
+// (with a one-site halo) is staged in LDS at a time (double buffered, loaded
+// one plane ahead into registers); every thread reads the 3 x 3 records
+// around its column once and adds their contributions to the three
+// destination planes they reach: p - 1 (complete after this plane, stored),
+// p and p + 1 (rolling accumulators).  Each record is read from memory about
+// once (plus halo) and from LDS nine times instead of 26.  The Laplacian's
+// terms k (phi_n - phi_0) for destination p + 1 arrive before its phi_0: they
+// are summed relative to the thread's own phi of plane p and corrected by the
+// weight sum (36) times the difference once phi_0 is known, so FP32 adds only
+// small differences.
 constexpr int kUpdRows = 8;
 
 template <typename C>
@@ -138,7 +146,11 @@ __global__ void __launch_bounds__(64 * kUpdRows) update_kernel(const Rec<C>* __r
                                                                int tiles_y, int zchunk,
                                                                bool walls_y) {
   constexpr int RY = kUpdRows + 2, RX = 66;
-  __shared__ Rec<C> t[3][RY][RX];
+  constexpr int NT = 64 * kUpdRows;           // threads
+  constexpr int NE = RY * RX;                 // staged records per plane
+  constexpr int PER = (NE + NT - 1) / NT;     // staged records per thread
+  constexpr int KZ = 16 + 4 * 4 + 4 * 1;      // sum of k over the 9 sites of an adjacent plane
+  __shared__ Rec<C> t[2][RY][RX];
   const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
   int b = static_cast<int>(blockIdx.x);
   const int tx = b % tiles_x;
@@ -148,51 +160,91 @@ __global__ void __launch_bounds__(64 * kUpdRows) update_kernel(const Rec<C>* __r
   const int x0 = tx * 64, y0 = ty * kUpdRows;
   const int z0 = zc * zchunk, z1 = min(z0 + zchunk, nz);
   const int64_t plane = static_cast<int64_t>(nx) * ny;
-  auto slot = [](int z) { return (z + 3) % 3; };  // z >= -1
-  auto load_plane = [&](int z) {
+  // this thread's staged records: in-plane offset, LDS position, and whether
+  // it is the mirror image beyond a y wall (flux normal to the wall reversed)
+  int64_t off[PER];
+  int pos[PER];
+  bool act[PER], ghost[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + k * NT;
+    act[k] = e < NE;
+    const int ry = act[k] ? e / RX : 0, rx = act[k] ? e - ry * RX : 0;
+    const int xw = pmod(x0 + rx - 1, nx), yr = y0 + ry - 1;
+    ghost[k] = walls_y && (yr < 0 || yr >= ny);
+    const int yw = walls_y ? clampi(yr, 0, ny - 1) : pmod(yr, ny);
+    off[k] = static_cast<int64_t>(yw) * nx + xw;
+    pos[k] = ry * RX + rx;
+  }
+  Rec<C> r[PER];
+  auto fetch = [&](int z) {
     const int64_t zb = static_cast<int64_t>(wrap(z, nz)) * plane;
-    Rec<C>(*dst)[RX] = t[slot(z)];
-    for (int e = threadIdx.x; e < RY * RX; e += 64 * kUpdRows) {
-      const int ry = e / RX, rx = e - ry * RX;
-      const int xw = pmod(x0 + rx - 1, nx), yr = y0 + ry - 1;
-      // beyond a y wall: the mirror image, its flux normal to the wall reversed
-      const bool ghost = walls_y && (yr < 0 || yr >= ny);
-      const int yw = walls_y ? clampi(yr, 0, ny - 1) : pmod(yr, ny);
-      Rec<C> v = V[zb + static_cast<int64_t>(yw) * nx + xw];
-      if (ghost) v.vy = -v.vy;
-      dst[ry][rx] = v;
-    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k)
+      if (act[k]) r[k] = V[zb + off[k]];
+  };
+  auto put = [&](int z) {
+    Rec<C>* dst = &t[z & 1][0][0];
+#pragma unroll
+    for (int k = 0; k < PER; ++k)
+      if (act[k]) {
+        Rec<C> v = r[k];
+        if (ghost[k]) v.vy = -v.vy;
+        dst[pos[k]] = v;
+      }
   };
   const int x = x0 + lane, y = y0 + wy;
   const bool mine = x < nx && y < ny;
-  load_plane(z0 - 1);
-  load_plane(z0);
-  for (int z = z0; z < z1; ++z) {
-    load_plane(z + 1);
+  // destination p - 1: divergence and Laplacian sums and its phi_0; p: the
+  // same, with the Laplacian part from plane p - 1 relative to ref0; p + 1
+  // is started afresh from each plane
+  C dvm = 0, lm = 0, pm = 0;
+  C dv0 = 0, l0 = 0, ref0 = 0;
+  fetch(z0 - 1);
+  for (int p = z0 - 1; p <= z1; ++p) {
+    put(p);  // plane p (fetched one iteration ahead)
     __syncthreads();
-    if (mine) {
-      const C p0 = t[slot(z)][wy + 1][lane + 1].phi;
-      C dv = 0, l = 0;
+    if (p < z1) fetch(p + 1);  // in flight while plane p is summed
+    Rec<C> q[3][3];
 #pragma unroll
-      for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-        for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = 0; dx < 3; ++dx) q[dy][dx] = t[p & 1][wy + dy][lane + dx];
+    const C own = q[1][1].phi;
+    C dvu = 0, lu = 0, dvc = 0, lc = 0, dvd = 0, ld = 0;
 #pragma unroll
-          for (int dx = -1; dx <= 1; ++dx) {
-            if (dx == 0 && dy == 0 && dz == 0) continue;
-            const Rec<C> r = t[slot(z + dz)][wy + 1 + dy][lane + 1 + dx];
-            const C k = C(k27(dx, dy, dz));
-            C cv = 0;
-            if (dx) cv += C(dx) * r.vx;
-            if (dy) cv += C(dy) * r.vy;
-            if (dz) cv += C(dz) * r.vz;
-            dv += k * cv;
-            l += k * (r.phi - p0);
-          }
-      out[static_cast<int64_t>(z) * plane + static_cast<int64_t>(y) * nx + x] =
-          p0 - div_by<72>(dv) + D * div_by<36>(l);
-    }
-    __syncthreads();
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const Rec<C>& n = q[dy + 1][dx + 1];
+        C cv = 0;
+        if (dx) cv += C(dx) * n.vx;
+        if (dy) cv += C(dy) * n.vy;
+        // seen from destination p + 1 this site is at dz = -1, from p - 1 at
+        // dz = +1, from p at dz = 0
+        const C ku = C(k27(dx, dy, 1));
+        dvu += ku * (cv - n.vz);
+        dvd += ku * (cv + n.vz);
+        lu += ku * (n.phi - own);
+        ld += ku * (n.phi - pm);
+        if (dx || dy) {
+          const C kc = C(k27(dx, dy, 0));
+          dvc += kc * cv;
+          lc += kc * (n.phi - own);
+        }
+      }
+    // destination p - 1 is complete
+    if (mine && p - 1 >= z0 && p - 1 < z1)
+      out[static_cast<int64_t>(p - 1) * plane + static_cast<int64_t>(y) * nx + x] =
+          pm - div_by<72>(dvm + dvd) + D * div_by<36>(lm + ld);
+    // destination p: the part from p - 1, corrected to phi_0 = own
+    dvm = dv0 + dvc;
+    lm = l0 - C(KZ) * (own - ref0) + lc;
+    pm = own;
+    // destination p + 1, relative to own
+    dv0 = dvu;
+    l0 = lu;
+    ref0 = own;
   }
 }
 
