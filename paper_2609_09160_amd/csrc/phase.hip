@@ -20,11 +20,13 @@
 //
 // Two passes per step advance phi: the total flux V = phi u + lambda J (J the
 // normalised compression flux) at every site, stored with phi as one 4-wide
-// record, then phi' = phi - div(V) + D lap(phi) by a z-march with the records
-// staged in LDS.  The flux and force passes take one thread per site and read
-// their 26 neighbours through the caches.  Algorithmic traffic at FP32: flux
-// 32 B per lattice update (phi, u in; record out), update 20 B (record in;
-// phi out), force 16 B (phi in, F out), against the fused step's 104.
+// record, then phi' = phi - div(V) + D lap(phi).  A third pass gives the force
+// from phi(t+1).  All three are z-marches over 64 x 8 column tiles that stage
+// one plane (with halo) in LDS at a time and add each plane's contributions
+// to the three destination planes it reaches, so a value is read from memory
+// about once.  Algorithmic traffic at FP32: flux 32 B per lattice update
+// (phi, u in; record out), update 20 B (record in; phi out), force 16 B (phi
+// in, F out), against the fused step's 104.
 #include "internal.hpp"
 #include "lattice.hpp"
 
@@ -39,59 +41,6 @@ __device__ constexpr int k27(int dx, int dy, int dz) {
   return c2 == 0 ? 64 : (c2 == 1 ? 16 : (c2 == 2 ? 4 : 1));
 }
 
-// neighbour offsets of site (x, y, z): ox[d+1] etc.; periodic, or with
-// halfway walls in y (walls_y) where the site beyond a wall is the mirror
-// image of the one next to it
-struct Nbr {
-  int64_t ox[3], oy[3], oz[3];
-  int64_t s;
-};
-
-__device__ __forceinline__ Nbr neighbours(int64_t s, int nx, int ny, int nz, bool walls_y) {
-  Nbr n;
-  const int64_t plane = static_cast<int64_t>(nx) * ny;
-  const int z = static_cast<int>(s / plane);
-  const int64_t r = s - static_cast<int64_t>(z) * plane;
-  const int y = static_cast<int>(r / nx);
-  const int x = static_cast<int>(r - static_cast<int64_t>(y) * nx);
-  for (int d = -1; d <= 1; ++d) {
-    n.ox[d + 1] = wrap(x + d, nx);
-    n.oy[d + 1] = static_cast<int64_t>(walls_y ? clampi(y + d, 0, ny - 1) : wrap(y + d, ny)) * nx;
-    n.oz[d + 1] = static_cast<int64_t>(wrap(z + d, nz)) * plane;
-  }
-  n.s = s;
-  return n;
-}
-
-__device__ __forceinline__ int64_t at(const Nbr& n, int dx, int dy, int dz) {
-  return n.ox[dx + 1] + n.oy[dy + 1] + n.oz[dz + 1];
-}
-
-// grad and lap of a scalar field at one site
-template <typename C>
-__device__ __forceinline__ void grad_lap(const C* __restrict__ f, const Nbr& n, C g[3], C& lap) {
-  const C f0 = f[n.s];
-  C gx = 0, gy = 0, gz = 0, l = 0;
-#pragma unroll
-  for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-    for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) {
-        if (dx == 0 && dy == 0 && dz == 0) continue;
-        const C v = f[at(n, dx, dy, dz)];
-        const C k = C(k27(dx, dy, dz));
-        gx += C(dx) * k * v;
-        gy += C(dy) * k * v;
-        gz += C(dz) * k * v;
-        l += k * (v - f0);
-      }
-  g[0] = div_by<72>(gx);
-  g[1] = div_by<72>(gy);
-  g[2] = div_by<72>(gz);
-  lap = div_by<36>(l);
-}
-
 // per-site record of the update pass: the total phase flux
 // V = phi u + lambda phi (1 - phi) grad(phi) / (|grad phi| + eps) (advection plus
 // interface compression, so that Eq. (2) reads phi' = phi - div(V) + D lap(phi))
@@ -101,20 +50,18 @@ struct alignas(4 * sizeof(C)) Rec {
   C vx, vy, vz, phi;
 };
 
+// Output of the flux pass at one site, from phi and its derivatives: the
+// record (V, phi) with u read from the state
 template <int ST>
-__global__ void __launch_bounds__(kPhaseThreads) flux_kernel(
-    const typename Storage<ST>::C* __restrict__ phi, const typename Storage<ST>::T* __restrict__ st,
-    Rec<typename Storage<ST>::C>* __restrict__ V, int nx, int ny, int nz, int64_t N,
-    typename Storage<ST>::C lambda, typename Storage<ST>::C eps, float s1, float s2, float s3,
-    bool walls_y) {
+struct FluxEmit {
   using S = Storage<ST>;
   using C = typename S::C;
-  for (int64_t s = blockIdx.x * static_cast<int64_t>(kPhaseThreads) + threadIdx.x; s < N;
-       s += static_cast<int64_t>(gridDim.x) * kPhaseThreads) {
-    const Nbr n = neighbours(s, nx, ny, nz, walls_y);
-    C g[3], l;
-    grad_lap(phi, n, g, l);
-    const C p = phi[s];
+  const typename S::T* st;
+  Rec<C>* V;
+  int64_t N;
+  C lambda, eps;
+  float s1, s2, s3;
+  __device__ __forceinline__ void operator()(int64_t s, C p, const C g[3], C) const {
     const C c = lambda * p * (C(1) - p) / (sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + eps);
     Rec<C> r;
     r.vx = p * S::load(st + N, s, s1) + c * g[0];
@@ -123,7 +70,7 @@ __global__ void __launch_bounds__(kPhaseThreads) flux_kernel(
     r.phi = p;
     V[s] = r;
   }
-}
+};
 
 // phi' = phi - div(V) + D lap(phi).  A workgroup owns a 64 x kUpdRows column
 // tile and a chunk of z-planes and marches through z.  One plane of records
@@ -248,30 +195,28 @@ __global__ void __launch_bounds__(64 * kUpdRows) update_kernel(const Rec<C>* __r
   }
 }
 
-// F = mu grad(phi) + rho(phi) g, plus (contrast) the pressure and viscous
-// terms - p* cs^2 grad(rho) - (nu omega / cs^2) (a2 - u u) . grad(rho), with
-// p*, u, a2 of the state at the previous time level
+// Output of the force pass at one site: F = mu grad(phi) + rho(phi) g, plus
+// (contrast) the pressure and viscous terms - p* cs^2 grad(rho)
+// - (nu omega / cs^2) (a2 - u u) . grad(rho), with p*, u, a2 of the state at
+// the previous time level
 template <int ST, bool CONTRAST>
-__global__ void __launch_bounds__(kPhaseThreads) force_kernel(
-    const typename Storage<ST>::C* __restrict__ phi, const typename Storage<ST>::T* __restrict__ st,
-    typename Storage<ST>::C* __restrict__ F, int nx, int ny, int nz, int64_t N, PhaseArgs pa) {
+struct ForceEmit {
   using S = Storage<ST>;
   using C = typename S::C;
-  const C beta = static_cast<C>(pa.beta), kappa = static_cast<C>(pa.kappa);
-  const C rl = static_cast<C>(pa.rho_l), dr = static_cast<C>(pa.rho_h - pa.rho_l);
-  const C nl = static_cast<C>(pa.nu_l), dn = static_cast<C>(pa.nu_h - pa.nu_l);
-  for (int64_t s = blockIdx.x * static_cast<int64_t>(kPhaseThreads) + threadIdx.x; s < N;
-       s += static_cast<int64_t>(gridDim.x) * kPhaseThreads) {
-    const Nbr n = neighbours(s, nx, ny, nz, pa.walls_y != 0);
-    C g[3], l;
-    grad_lap(phi, n, g, l);
-    const C p = phi[s];
+  const typename S::T* st;
+  C* F;
+  int64_t N;
+  PhaseArgs pa;
+  __device__ __forceinline__ void operator()(int64_t s, C p, const C g[3], C l) const {
+    const C beta = static_cast<C>(pa.beta), kappa = static_cast<C>(pa.kappa);
+    const C rl = static_cast<C>(pa.rho_l), dr = static_cast<C>(pa.rho_h - pa.rho_l);
     const C mu = C(4) * beta * p * (p - C(1)) * (p - C(0.5)) - kappa * l;
     const C rho = rl + p * dr;
     C f[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) f[k] = mu * g[k] + rho * static_cast<C>(pa.Fb[k]);
     if constexpr (CONTRAST) {
+      const C nl = static_cast<C>(pa.nu_l), dn = static_cast<C>(pa.nu_h - pa.nu_l);
       C m[10];
 #pragma unroll
       for (int k = 0; k < 10; ++k) m[k] = S::load(st + k * N, s, pa.scale[k]);
@@ -294,6 +239,133 @@ __global__ void __launch_bounds__(kPhaseThreads) force_kernel(
     F[N + s] = f[1];
     F[2 * N + s] = f[2];
   }
+};
+
+// grad(phi) and lap(phi) at every site, handed to an output functor: the
+// same tiles, z-march, staging and 2.5-D accumulation as the update pass, on
+// the scalar phi (a y wall's ghost is the mirror value)
+template <typename C, class Emit>
+__global__ void __launch_bounds__(64 * kUpdRows) grad_march_kernel(const C* __restrict__ phi,
+                                                                   int nx, int ny, int nz,
+                                                                   int tiles_x, int tiles_y,
+                                                                   int zchunk, bool walls_y,
+                                                                   Emit emit) {
+  constexpr int RY = kUpdRows + 2, RX = 66;
+  constexpr int NT = 64 * kUpdRows;
+  constexpr int NE = RY * RX;
+  constexpr int PER = (NE + NT - 1) / NT;
+  constexpr int KZ = 16 + 4 * 4 + 4 * 1;  // sum of k over the 9 sites of an adjacent plane
+  __shared__ C t[2][RY][RX];
+  const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
+  int b = static_cast<int>(blockIdx.x);
+  const int tx = b % tiles_x;
+  b /= tiles_x;
+  const int ty = b % tiles_y;
+  const int zc = b / tiles_y;
+  const int x0 = tx * 64, y0 = ty * kUpdRows;
+  const int z0 = zc * zchunk, z1 = min(z0 + zchunk, nz);
+  const int64_t plane = static_cast<int64_t>(nx) * ny;
+  int64_t off[PER];
+  int pos[PER];
+  bool act[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + k * NT;
+    act[k] = e < NE;
+    const int ry = act[k] ? e / RX : 0, rx = act[k] ? e - ry * RX : 0;
+    const int xw = pmod(x0 + rx - 1, nx), yr = y0 + ry - 1;
+    const int yw = walls_y ? clampi(yr, 0, ny - 1) : pmod(yr, ny);
+    off[k] = static_cast<int64_t>(yw) * nx + xw;
+    pos[k] = ry * RX + rx;
+  }
+  C r[PER];
+  auto fetch = [&](int z) {
+    const int64_t zb = static_cast<int64_t>(wrap(z, nz)) * plane;
+#pragma unroll
+    for (int k = 0; k < PER; ++k)
+      if (act[k]) r[k] = phi[zb + off[k]];
+  };
+  auto put = [&](int z) {
+    C* dst = &t[z & 1][0][0];
+#pragma unroll
+    for (int k = 0; k < PER; ++k)
+      if (act[k]) dst[pos[k]] = r[k];
+  };
+  const int x = x0 + lane, y = y0 + wy;
+  const bool mine = x < nx && y < ny;
+  // destination p - 1 (sums and phi_0) and p (sums from plane p - 1, the
+  // Laplacian relative to ref0), as in the update pass
+  C gxm = 0, gym = 0, gzm = 0, lm = 0, pm = 0;
+  C gx0 = 0, gy0 = 0, gz0 = 0, l0 = 0, ref0 = 0;
+  fetch(z0 - 1);
+  for (int p = z0 - 1; p <= z1; ++p) {
+    put(p);
+    __syncthreads();
+    if (p < z1) fetch(p + 1);
+    C q[3][3];
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) q[dy][dx] = t[p & 1][wy + dy][lane + dx];
+    const C own = q[1][1];
+    // sums over this plane's 3 x 3 sites with the weights of an adjacent
+    // plane (ku) and of the own plane (kc, centre excluded)
+    C axu = 0, ayu = 0, azu = 0, lu = 0, ld = 0, axc = 0, ayc = 0, lc = 0;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const C n = q[dy + 1][dx + 1];
+        const C ku = C(k27(dx, dy, 1));
+        if (dx) axu += C(dx) * ku * n;
+        if (dy) ayu += C(dy) * ku * n;
+        azu += ku * n;
+        lu += ku * (n - own);
+        ld += ku * (n - pm);
+        if (dx || dy) {
+          const C kc = C(k27(dx, dy, 0));
+          if (dx) axc += C(dx) * kc * n;
+          if (dy) ayc += C(dy) * kc * n;
+          lc += kc * (n - own);
+        }
+      }
+    // destination p - 1 is complete: this plane is at dz = +1 from it
+    if (mine && p - 1 >= z0 && p - 1 < z1) {
+      const C g[3] = {div_by<72>(gxm + axu), div_by<72>(gym + ayu), div_by<72>(gzm + azu)};
+      emit(static_cast<int64_t>(p - 1) * plane + static_cast<int64_t>(y) * nx + x, pm, g,
+           div_by<36>(lm + ld));
+    }
+    // destination p: plane p - 1 (at dz = -1) plus this plane
+    gxm = gx0 + axc;
+    gym = gy0 + ayc;
+    gzm = gz0;
+    lm = l0 - C(KZ) * (own - ref0) + lc;
+    pm = own;
+    // destination p + 1: this plane at dz = -1
+    gx0 = axu;
+    gy0 = ayu;
+    gz0 = -azu;
+    l0 = lu;
+    ref0 = own;
+  }
+}
+
+// tiles and z-chunks of the staged passes: 64 x kUpdRows columns, chunks of
+// >= 8 planes for about 512 workgroups
+struct MarchGeom {
+  int tiles_x, tiles_y, zchunk, blocks;
+};
+MarchGeom march_geom(int nx, int ny, int nz) {
+  MarchGeom m;
+  m.tiles_x = (nx + 63) / 64;
+  m.tiles_y = (ny + kUpdRows - 1) / kUpdRows;
+  const int cols = m.tiles_x * m.tiles_y;
+  int nch = (512 + cols - 1) / cols;
+  const int maxc = nz >= 8 ? nz / 8 : 1;
+  nch = nch < 1 ? 1 : (nch > maxc ? maxc : nch);
+  m.zchunk = (nz + nch - 1) / nch;
+  m.blocks = cols * ((nz + m.zchunk - 1) / m.zchunk);
+  return m;
 }
 
 int phase_grid(int64_t N) {
@@ -305,22 +377,16 @@ template <int ST>
 hipError_t phase_step_st(const PhaseArgs& a, hipStream_t s) {
   using C = typename Storage<ST>::C;
   using T = typename Storage<ST>::T;
-  const dim3 grid(phase_grid(a.N)), block(kPhaseThreads);
-  hipLaunchKernelGGL((flux_kernel<ST>), grid, block, 0, s, static_cast<const C*>(a.phi),
-                     static_cast<const T*>(a.state), static_cast<Rec<C>*>(a.J), a.nx, a.ny, a.nz,
-                     a.N, static_cast<C>(a.lambda), static_cast<C>(a.eps), a.scale[1], a.scale[2],
-                     a.scale[3], a.walls_y != 0);
-  // update: 64 x 8 column tiles, z-chunks of >= 8 planes for ~512 workgroups
-  const int tiles_x = (a.nx + 63) / 64, tiles_y = (a.ny + kUpdRows - 1) / kUpdRows;
-  const int cols = tiles_x * tiles_y;
-  int nch = (512 + cols - 1) / cols;
-  const int maxc = a.nz >= 8 ? a.nz / 8 : 1;
-  nch = nch < 1 ? 1 : (nch > maxc ? maxc : nch);
-  const int zchunk = (a.nz + nch - 1) / nch;
-  const int zchunks = (a.nz + zchunk - 1) / zchunk;
-  hipLaunchKernelGGL((update_kernel<C>), dim3(cols * zchunks), dim3(64 * kUpdRows), 0, s,
+  const MarchGeom m = march_geom(a.nx, a.ny, a.nz);
+  const FluxEmit<ST> flux{static_cast<const T*>(a.state), static_cast<Rec<C>*>(a.J), a.N,
+                          static_cast<C>(a.lambda), static_cast<C>(a.eps), a.scale[1],
+                          a.scale[2], a.scale[3]};
+  hipLaunchKernelGGL((grad_march_kernel<C, FluxEmit<ST>>), dim3(m.blocks), dim3(64 * kUpdRows),
+                     0, s, static_cast<const C*>(a.phi), a.nx, a.ny, a.nz, m.tiles_x, m.tiles_y,
+                     m.zchunk, a.walls_y != 0, flux);
+  hipLaunchKernelGGL((update_kernel<C>), dim3(m.blocks), dim3(64 * kUpdRows), 0, s,
                      static_cast<const Rec<C>*>(a.J), static_cast<C*>(a.phi_out), a.nx, a.ny,
-                     a.nz, static_cast<C>(a.D), tiles_x, tiles_y, zchunk, a.walls_y != 0);
+                     a.nz, static_cast<C>(a.D), m.tiles_x, m.tiles_y, m.zchunk, a.walls_y != 0);
   return hipGetLastError();
 }
 
@@ -341,15 +407,19 @@ template <int ST>
 hipError_t force_st(const PhaseArgs& a, hipStream_t s) {
   using C = typename Storage<ST>::C;
   using T = typename Storage<ST>::T;
-  const dim3 grid(phase_grid(a.N)), block(kPhaseThreads);
+  const MarchGeom m = march_geom(a.nx, a.ny, a.nz);
+  const C* phi = static_cast<const C*>(a.phi_out);
+  const T* st = static_cast<const T*>(a.state);
   if (a.contrast)
-    hipLaunchKernelGGL((force_kernel<ST, true>), grid, block, 0, s,
-                       static_cast<const C*>(a.phi_out), static_cast<const T*>(a.state),
-                       static_cast<C*>(a.F), a.nx, a.ny, a.nz, a.N, a);
+    hipLaunchKernelGGL((grad_march_kernel<C, ForceEmit<ST, true>>), dim3(m.blocks),
+                       dim3(64 * kUpdRows), 0, s, phi, a.nx, a.ny, a.nz, m.tiles_x, m.tiles_y,
+                       m.zchunk, a.walls_y != 0,
+                       ForceEmit<ST, true>{st, static_cast<C*>(a.F), a.N, a});
   else
-    hipLaunchKernelGGL((force_kernel<ST, false>), grid, block, 0, s,
-                       static_cast<const C*>(a.phi_out), static_cast<const T*>(a.state),
-                       static_cast<C*>(a.F), a.nx, a.ny, a.nz, a.N, a);
+    hipLaunchKernelGGL((grad_march_kernel<C, ForceEmit<ST, false>>), dim3(m.blocks),
+                       dim3(64 * kUpdRows), 0, s, phi, a.nx, a.ny, a.nz, m.tiles_x, m.tiles_y,
+                       m.zchunk, a.walls_y != 0,
+                       ForceEmit<ST, false>{st, static_cast<C*>(a.F), a.N, a});
   return hipGetLastError();
 }
 }  // namespace
