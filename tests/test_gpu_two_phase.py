@@ -95,6 +95,34 @@ def test_two_phase_parity_fp64(Q, sites):
     assert em <= 1e-12 and ep <= 1e-12
 
 
+@pytest.mark.parametrize("shape", [(7, 5, 3), (3, 2, 1), (65, 9, 2), (1, 17, 9)])
+@pytest.mark.parametrize("walls", [False, True])
+def test_two_phase_small_and_thin_grids(shape, walls):
+    """Grids smaller than one 64 x 8 stencil tile, a single z-plane, two
+    z-planes and a single x column, periodic or walled in y: the staged
+    phase-field passes (one plane of records in LDS, rolling accumulators
+    over three destination planes) wrap and mirror their halos within the
+    grid.  Random phase field in [0.2, 0.8] and off-equilibrium flow, density
+    and viscosity contrast, 5 steps, FP64: element-wise against the oracle."""
+    if walls and shape[1] < 2:
+        pytest.skip("a walled axis needs >= 2 sites")
+    nx, ny, nz = shape
+    rng = np.random.default_rng(sum(shape) + 7 * walls)
+    phi0 = 0.2 + 0.6 * rng.random((nz, ny, nx))
+    m0, _ = _droplet_state(shape, 1, seed=sum(shape))
+    bc = (0, 1 if walls else 0, 0)
+    g = (2e-6, -1e-6, 5e-7)
+    say(f"two-phase small grid {shape} walls={walls}")
+    got, gphi, _ = gpu_two_phase(shape, 1.0, m0, phi0, 5, force=g, bc=bc, rho=(0.5, 1.5),
+                                 taus=(0.65, 1.7))
+    want, wphi = oracle_two_phase(shape, 1.0, m0, phi0, 5, force=np.array(g), bc=bc,
+                                  rho=(0.5, 1.5), nu=(0.05, 0.4))
+    em = group_rel_err(got, want)
+    ep = float(np.abs(gphi - wphi).max() / np.abs(wphi).max())
+    say(f"  moments {em:.2e}, phi {ep:.2e}")
+    assert em <= 1e-12 and ep <= 1e-12
+
+
 @pytest.mark.parametrize("steps", [100, 600])
 def test_two_phase_parity_fp32_laplace_32(steps):
     """The oracle's Laplace case (32^3, R = 8, tau = 1, from rest) in FP32
