@@ -193,6 +193,36 @@ def stream_ceiling(n=512 ** 3, nplanes=10, reps=5):
     return nbytes / (ms * 1e-3) / 1e9, ms, nbytes
 
 
+def copy_ceiling(n=512 ** 3, nplanes=10, reps=5):
+    """The fastest copy form measured on MI355X (one 16-byte access per lane,
+    non-temporal stores) over nplanes x n floats: GB/s counting read + write,
+    the ceiling of a stream that reads and writes equal volumes."""
+    import ctypes
+    import torch
+    from paper_2609_09160_amd import _lib
+    lib = _lib.load()
+    a = torch.ones(nplanes * n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
+    args = (ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), nplanes * n // 4,
+            ctypes.c_void_p(stream.cuda_stream))
+    _lib.check(lib.lbfast_copy_probe(*args))
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        st, en = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        st.record(stream)
+        _lib.check(lib.lbfast_copy_probe(*args))
+        en.record(stream)
+        torch.cuda.synchronize()
+        ms = st.elapsed_time(en)
+        best = ms if best is None else min(best, ms)
+    assert torch.equal(a[-1024:], b[-1024:])
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * 4 * nplanes * n / (best * 1e-3) / 1e9
+
+
 ADJ_BYTES_PER_LUP = 140   # adjoint step: read lambda' 40, F 12, u(t+1) 12, u(t) 12, gF 12;
                           # write lambda 40, gF 12 (FP32)
 FWD_F_BYTES_PER_LUP = 92  # forward step with a per-site force field: 40 + 12 read, 40 written
@@ -419,6 +449,9 @@ def main():
     gbs, _, _ = stream_ceiling()
     out["roofline"]["measured_stream_GBs"] = round(gbs, 1)
     out["roofline"]["frac_of_measured_stream"] = round(achieved / gbs, 4)
+    cgbs = copy_ceiling()
+    out["roofline"]["measured_copy_GBs"] = round(cgbs, 1)
+    out["roofline"]["frac_of_measured_copy"] = round(achieved / cgbs, 4)
     if not args.no_variants:
         var = {}
         for lat, st in ((27, "f32"), (19, "f16s"), (19, "bf16s"), (27, "f16s"), (19, "f64"),

@@ -247,6 +247,13 @@ int lbfast_adjoint(lbfast_t h, int64_t nsteps, int64_t every, const void* ckpt_d
  * hardware traffic counters against the step. */
 int lbfast_stream_probe(const void* src, void* dst, int64_t n, int nplanes, void* stream);
 
+/* Measurement utility, not part of the method: copy n4 16-byte elements from
+ * src to dst (device pointers, 16-byte aligned) on `stream` with one 16-byte
+ * access per lane and non-temporal stores, the fastest copy form measured on
+ * MI355X: the bandwidth ceiling of a stream that reads and writes equal
+ * volumes, against which the step's achieved bandwidth is set. */
+int lbfast_copy_probe(const void* src, void* dst, int64_t n4, void* stream);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char* lbfast_last_error(void);
 

@@ -79,6 +79,7 @@ def load():
         "lbfast_set_lane_sites": ([vp, i32], i32),
         "lbfast_last_error": ([], ctypes.c_char_p),
         "lbfast_stream_probe": ([vp, vp, i64, i32, vp], i32),
+        "lbfast_copy_probe": ([vp, vp, i64, vp], i32),
         "lbfast_enable_two_phase": ([vp, ctypes.POINTER(LbfastPhaseParams)], i32),
         "lbfast_set_phase": ([vp, vp, i32, i32], i32),
         "lbfast_get_phase": ([vp, vp, i32, i32], i32),

@@ -15,6 +15,11 @@
 
 #include "internal.hpp"
 
+namespace lbf {
+// measurement utility, aux.hip
+hipError_t launch_copy_probe(const void* src, void* dst, int64_t n4, hipStream_t s);
+}  // namespace lbf
+
 namespace {
 
 thread_local std::string g_err;
@@ -308,6 +313,17 @@ int lbfast_stream_probe(const void* src, void* dst, int64_t n, int nplanes, void
   if (nplanes < 1) return fail(LBF_E_ARG, "nplanes must be >= 1");
   hipError_t e = lbf::launch_stream_probe(src, dst, n, nplanes, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "stream probe");
+  return LBF_OK;
+}
+
+int lbfast_copy_probe(const void* src, void* dst, int64_t n4, void* stream) {
+  g_err.clear();
+  if (!src || !dst) return fail(LBF_E_ARG, "null buffer");
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15)
+    return fail(LBF_E_ARG, "buffers must be 16-byte aligned");
+  if (n4 < 1) return fail(LBF_E_ARG, "n4 must be >= 1");
+  hipError_t e = lbf::launch_copy_probe(src, dst, n4, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "copy probe");
   return LBF_OK;
 }
 
