@@ -151,7 +151,11 @@ int lbfast_get_scales(lbfast_t h, float out[10]);
 /* Launch shape: rows per tile (4, 6, 8 or 14 -- at most 8 with two sites
  * per lane or with LBF_D3Q27H; LBF_E_UNSUPPORTED if the tile's LDS would
  * exceed 160 KiB) and z-planes per workgroup (>= 1); 0 keeps
- * the current value.  Every shape computes the same formulas per site; the
+ * the current value.  The default z-planes per workgroup follow the grid: at
+ * most ~512 workgroups (~1024 for F64 with two sites per lane) in chunks of
+ * >= 64 planes, or, where that leaves fewer than 128 workgroups, enough
+ * workgroups in chunks of >= 8 planes; a z_chunk set here replaces that rule.
+ * Every shape computes the same formulas per site; the
  * tile heights are separately compiled, so results may differ between shapes
  * in the last bits (floating-point contraction), while one shape is bitwise
  * reproducible from run to run. */
@@ -159,7 +163,9 @@ int lbfast_set_launch(lbfast_t h, int tile_rows, int z_chunk);
 
 /* Consecutive x-sites per lane: 1 (64-wide tiles) or 2 (128-wide tiles, one
  * 2-wide load or store per moment plane; needs an even nx and tiles of at
- * most 8 rows).  The default is 2 where nx is even and at least 128.  If the
+ * most 8 rows).  The default is 2 where nx is even and at least 128 and the
+ * 128-wide tiles leave no more of the last tile empty than 64-wide ones (1
+ * for LBF_D3Q27H with F64 storage, where two sites spill registers).  If the
  * current tile height does not fit the 160 KiB of LDS with the new setting,
  * the tallest of 8, 6 and 4 rows that does is taken.  Same formulas per site;
  * results may differ between settings in the last bits. */
