@@ -300,9 +300,9 @@ def run_adjoint(n=192, steps=500, reps=2):
             "finite": fin1 and fin50}
 
 
-TP_BYTES_PER_LUP = 172  # two-component step, FP32: fused step with F(t) and F(t+1) 104;
-                        # phase flux 32 (phi, u in; flux and phi record out); phase
-                        # update 20 (record in; phi out); capillary force 16 (phi in, F out)
+TP_BYTES_PER_LUP = 140  # two-component step, FP32: fused step with F(t) and F(t+1) 104;
+                        # phase update 20 (phi, u in; phi out); capillary force 16 (phi
+                        # in, F out)
 TP_CONTRAST_EXTRA = 48  # with density contrast: phi(t), phi(t+1) read by the fused step 8;
                         # the force pass reads the 10 moments of the state 40
 

@@ -52,7 +52,6 @@ struct PhaseArgs {
   const void* phi;    // phi(t), N values of C
   void* phi_out;      // phi(t+1)
   const void* state;  // moment buffer at t (its velocity planes are read)
-  void* J;            // scratch: 4 x N values of C (per-site records: phase flux, phi)
   void* F;            // receives F(t+1): 3 planes of C
   int nx, ny, nz;
   int64_t N;

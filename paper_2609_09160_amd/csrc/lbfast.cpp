@@ -117,7 +117,6 @@ struct lbfast_ctx {
   lbfast_phase_params pp;
   void* phi[2] = {nullptr, nullptr};  // phase field, two time levels
   void* Fph[2] = {nullptr, nullptr};  // force of the two time levels (3 planes)
-  void* Jph = nullptr;                // phase-flux records (4 x N)
   int pcur = 0;
   double* d_partials = nullptr;  // kReduceBlocks*5 + 5 doubles
   unsigned* d_maxbits = nullptr; // 10
@@ -262,7 +261,6 @@ lbf::PhaseArgs phase_args(const lbfast_ctx* h) {
   a.phi = h->phi[h->pcur];
   a.phi_out = h->phi[h->pcur ^ 1];
   a.state = h->buf[h->cur];
-  a.J = h->Jph;
   a.F = h->Fph[h->pcur ^ 1];
   a.nx = static_cast<int>(h->p.nx);
   a.ny = static_cast<int>(h->p.ny);
@@ -414,7 +412,7 @@ int lbfast_destroy(lbfast_t h) {
     if (h->buf[0]) (void)hipFree(h->buf[0]);
     if (h->buf[1]) (void)hipFree(h->buf[1]);
   }
-  for (void* p : {h->phi[0], h->phi[1], h->Fph[0], h->Fph[1], h->Jph})
+  for (void* p : {h->phi[0], h->phi[1], h->Fph[0], h->Fph[1]})
     if (p) (void)hipFree(p);
   if (h->d_partials) (void)hipFree(h->d_partials);
   if (h->d_maxbits) (void)hipFree(h->d_maxbits);
@@ -667,14 +665,14 @@ int lbfast_enable_two_phase(lbfast_t h, const lbfast_phase_params* pp) {
   const size_t c = compute_bytes(h);
   const size_t pb = static_cast<size_t>(h->N) * c;
   hipError_t e = hipSuccess;
-  void** slots[5] = {&h->phi[0], &h->phi[1], &h->Fph[0], &h->Fph[1], &h->Jph};
-  const size_t sizes[5] = {pb, pb, 3 * pb, 3 * pb, 4 * pb};
-  for (int i = 0; i < 5 && e == hipSuccess; ++i) e = hipMalloc(slots[i], sizes[i]);
-  for (int i = 0; i < 5 && e == hipSuccess; ++i)
+  void** slots[4] = {&h->phi[0], &h->phi[1], &h->Fph[0], &h->Fph[1]};
+  const size_t sizes[4] = {pb, pb, 3 * pb, 3 * pb};
+  for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipMalloc(slots[i], sizes[i]);
+  for (int i = 0; i < 4 && e == hipSuccess; ++i)
     e = lbf::launch_zero(*slots[i], static_cast<int64_t>(sizes[i]), h->stream);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 4; ++i)
       if (*slots[i]) {
         (void)hipFree(*slots[i]);
         *slots[i] = nullptr;
