@@ -32,10 +32,35 @@ namespace {
 
 constexpr int kPhaseThreads = 256;
 
-// D3Q27 stencil weight numerators (w = k / 216) by |c|^2
-__device__ constexpr int k27(int dx, int dy, int dz) {
-  const int c2 = dx * dx + dy * dy + dz * dz;
-  return c2 == 0 ? 64 : (c2 == 1 ? 16 : (c2 == 2 ? 4 : 1));
+// The stencil weights factor: k(dx, dy, dz) = k1(dx) k1(dy) k1(dz) with
+// k1(0) = 4, k1(+-1) = 1.  So a plane's sums with the weights of an adjacent
+// plane (k1(+-1) = 1) are separable 3 x 3 sums, and with the own plane's
+// weights they are 4 times those.  On a 3 x 3 window n[dy][dx] (offsets -1..1):
+//   ss = sum k1 k1 n, ds = sum dx k1 k1 n, sd = sum dy k1 k1 n.
+template <typename C>
+__device__ __forceinline__ C sum141(C a, C b, C c) {
+  return a + C(4) * b + c;
+}
+template <typename C>
+__device__ __forceinline__ void window_sums(const C (&n)[3][3], C& ss, C& ds, C& sd) {
+  C sx[3], dx[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    sx[r] = sum141(n[r][0], n[r][1], n[r][2]);
+    dx[r] = n[r][2] - n[r][0];
+  }
+  ss = sum141(sx[0], sx[1], sx[2]);
+  ds = sum141(dx[0], dx[1], dx[2]);
+  sd = sx[2] - sx[0];
+}
+// sum k1 k1 (n - own), the centre being own: the differences are formed
+// first, so that FP32 adds small numbers
+template <typename C>
+__device__ __forceinline__ C window_lap(const C (&n)[3][3], C own) {
+  const C r0 = sum141(n[0][0] - own, n[0][1] - own, n[0][2] - own);
+  const C r1 = (n[1][0] - own) + (n[1][2] - own);
+  const C r2 = sum141(n[2][0] - own, n[2][1] - own, n[2][2] - own);
+  return sum141(r0, r1, r2);
 }
 
 // per-site record staged by the phase update: the total phase flux
@@ -58,6 +83,16 @@ struct alignas(4 * sizeof(C)) Rec {
 // corrected, once phi_0 is known, by the weight sum (36) times the
 // difference, so FP32 adds only small differences.
 constexpr int kUpdRows = 8;
+// Loads ahead of use in the staged marches.  Iterations run in groups of
+// kGroup planes, with two register banks: at the start of a group the next
+// group's values are issued into one bank, and the current group is taken
+// from the other.  So a value is loaded one to two groups before its use.
+// Only the loads issued at the start of the group are ever in flight at a
+// wait, even where the compiler's wait counting treats loads that cross
+// the loop's back edge as just issued.  Every load is unconditional: an
+// inactive slot reads offset 0, and a plane index past the chunk is clamped,
+// which re-reads a cached plane.  So the loads form one fixed sequence.
+constexpr int kGroup = 1;
 
 // The whole phase update in one z-march: phi' = phi - div(V) + D lap(phi)
 // with V = phi u + lambda phi (1 - phi) grad(phi) / (|grad phi| + eps), no
@@ -109,7 +144,7 @@ __global__ void __launch_bounds__(64 * kUpdRows) phase_kernel(
     const int ry = pact[k] ? e / PX : 0, rx = pact[k] ? e - ry * PX : 0;
     const int yr = y0 + ry - 2;
     const int yw = walls_y ? clampi(yr, 0, ny - 1) : pmod(yr, ny);
-    poff[k] = static_cast<int64_t>(yw) * nx + pmod(x0 + rx - 2, nx);
+    poff[k] = pact[k] ? static_cast<int64_t>(yw) * nx + pmod(x0 + rx - 2, nx) : 0;
   }
   // record slots: the source site (the mirror site for a ghost), the top-left
   // of its 3 x 3 phi window in the staged plane, and whether v_y is reversed.
@@ -127,31 +162,28 @@ __global__ void __launch_bounds__(64 * kUpdRows) phase_kernel(
     const int ys = walls_y ? clampi(yr, 0, ny - 1) : pmod(yr, ny);
     vneg[k] = walls_y && ys != yr;
     vwin[k] = (walls_y ? ys - y0 + 1 : ry) * PX + rx;
-    voff[k] = static_cast<int64_t>(ys) * nx + pmod(x0 + rx - 1, nx);
+    voff[k] = vact[k] ? static_cast<int64_t>(ys) * nx + pmod(x0 + rx - 1, nx) : 0;
   }
-  // phi and u are loaded two planes ahead into two register sets; the set of
-  // plane z is (z - z0) & 1, a compile-time index in the loop body below
-  using I0 = std::integral_constant<int, 0>;
-  using I1 = std::integral_constant<int, 1>;
-  C rp[2][PERP];
-  auto fetch_phi = [&](auto P, int z) {
-    constexpr int h = decltype(P)::value;
-    const int64_t zb = static_cast<int64_t>(pmod(z, nz)) * plane;
+  // register banks: slot i of a group starting at plane qs holds phi of
+  // plane qs + i and u of plane qs + i - 1 (for V(qs + i - 1))
+  constexpr int G = kGroup;
+  C rp[2][G][PERP];
+  C ux[2][G][PERV], uy[2][G][PERV], uz[2][G][PERV];
+  auto load_group = [&](auto B, int qs) {
+    constexpr int b = decltype(B)::value;
+    static_for<G>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      const int64_t zp = static_cast<int64_t>(pmod(min(qs + i, z1 + 1), nz)) * plane;
 #pragma unroll
-    for (int k = 0; k < PERP; ++k)
-      if (pact[k]) rp[h][k] = phi[zb + poff[k]];
-  };
-  C ux[2][PERV], uy[2][PERV], uz[2][PERV];
-  auto fetch_u = [&](auto P, int z) {
-    constexpr int h = decltype(P)::value;
-    const int64_t zb = static_cast<int64_t>(pmod(z, nz)) * plane;
+      for (int k = 0; k < PERP; ++k) rp[b][i][k] = phi[zp + poff[k]];
+      const int64_t zu = static_cast<int64_t>(pmod(clampi(qs + i - 1, z0 - 1, z1), nz)) * plane;
 #pragma unroll
-    for (int k = 0; k < PERV; ++k)
-      if (vact[k]) {
-        ux[h][k] = S::load(st + N, zb + voff[k], s1);
-        uy[h][k] = S::load(st + 2 * N, zb + voff[k], s2);
-        uz[h][k] = S::load(st + 3 * N, zb + voff[k], s3);
+      for (int k = 0; k < PERV; ++k) {
+        ux[b][i][k] = S::load(st + N, zu + voff[k], s1);
+        uy[b][i][k] = S::load(st + 2 * N, zu + voff[k], s2);
+        uz[b][i][k] = S::load(st + 3 * N, zu + voff[k], s3);
       }
+    });
   };
   // per slot: gradient sums of V(q) (m) and V(q + 1) (0), phi of V(q), and
   // the record V(q - 1) completed this iteration
@@ -160,7 +192,6 @@ __global__ void __launch_bounds__(64 * kUpdRows) phase_kernel(
 #pragma unroll
   for (int k = 0; k < PERV; ++k) {
     gxm[k] = gym[k] = gzm[k] = pv[k] = gx0[k] = gy0[k] = gz0[k] = C(0);
-    ux[0][k] = uy[0][k] = uz[0][k] = ux[1][k] = uy[1][k] = uz[1][k] = C(0);
     rv[k] = Rec<C>{C(0), C(0), C(0), C(0)};
   }
   const int x = x0 + lane, y = y0 + wy;
@@ -169,14 +200,13 @@ __global__ void __launch_bounds__(64 * kUpdRows) phase_kernel(
   // Laplacian of the latter relative to ref0
   C dvm = 0, lm = 0, pm = 0;
   C dv0 = 0, l0 = 0, ref0 = 0;
-  // iteration q; P = (q - z0) & 1 is the register set of plane q
-  auto body = [&](int q, auto P) {
-    constexpr int h = decltype(P)::value;
-    using Other = std::integral_constant<int, 1 - h>;
+  // iteration q, its values in slot I of bank B
+  auto body = [&](int q, auto B, auto I) {
+    constexpr int b = decltype(B)::value, i = decltype(I)::value;
     if (q <= z1 + 1) {
 #pragma unroll
       for (int k = 0; k < PERP; ++k)
-        if (pact[k]) tp[q & 1][threadIdx.x + k * NT] = rp[h][k];
+        if (pact[k]) tp[q & 1][threadIdx.x + k * NT] = rp[b][i][k];
     }
     if (q >= z0 + 1) {
 #pragma unroll
@@ -184,7 +214,6 @@ __global__ void __launch_bounds__(64 * kUpdRows) phase_kernel(
         if (vact[k]) tv[q & 1][threadIdx.x + k * NT] = rv[k];
     }
     __syncthreads();
-    if (q + 2 <= z1 + 1) fetch_phi(P, q + 2);  // in flight for two iterations
     if (q <= z1 + 1) {
       const C* w = tp[q & 1];
 #pragma unroll
@@ -195,76 +224,59 @@ __global__ void __launch_bounds__(64 * kUpdRows) phase_kernel(
           for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx) n[dy][dx] = w[vwin[k] + dy * PX + dx];
-          C axu = 0, ayu = 0, azu = 0, axc = 0, ayc = 0;
-#pragma unroll
-          for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) {
-              const C v = n[dy + 1][dx + 1];
-              const C ku = C(k27(dx, dy, 1));
-              if (dx) axu += C(dx) * ku * v;
-              if (dy) ayu += C(dy) * ku * v;
-              azu += ku * v;
-              if (dx || dy) {
-                const C kc = C(k27(dx, dy, 0));
-                if (dx) axc += C(dx) * kc * v;
-                if (dy) ayc += C(dy) * kc * v;
-              }
-            }
-          // V(q - 1) is complete: this plane is at dz = +1 from it; its u is
-          // in the other set
-          const C g[3] = {div_by<72>(gxm[k] + axu), div_by<72>(gym[k] + ayu),
-                          div_by<72>(gzm[k] + azu)};
+          C ss, ds, sd;
+          window_sums(n, ss, ds, sd);
+          // V(q - 1) is complete: this plane is at dz = +1 from it
+          const C g[3] = {div_by<72>(gxm[k] + ds), div_by<72>(gym[k] + sd),
+                          div_by<72>(gzm[k] + ss)};
           const C p = pv[k];
           const C c =
               lambda * p * (C(1) - p) / (sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + eps);
-          rv[k].vx = p * ux[1 - h][k] + c * g[0];
-          rv[k].vy = p * uy[1 - h][k] + c * g[1];
-          rv[k].vz = p * uz[1 - h][k] + c * g[2];
+          rv[k].vx = p * ux[b][i][k] + c * g[0];
+          rv[k].vy = p * uy[b][i][k] + c * g[1];
+          rv[k].vz = p * uz[b][i][k] + c * g[2];
           rv[k].phi = p;
           if (vneg[k]) rv[k].vy = -rv[k].vy;
           // V(q): plane q - 1 (at dz = -1) plus this plane; V(q + 1): this
           // plane at dz = -1
-          gxm[k] = gx0[k] + axc;
-          gym[k] = gy0[k] + ayc;
+          gxm[k] = gx0[k] + C(4) * ds;
+          gym[k] = gy0[k] + C(4) * sd;
           gzm[k] = gz0[k];
           pv[k] = n[1][1];
-          gx0[k] = axu;
-          gy0[k] = ayu;
-          gz0[k] = -azu;
+          gx0[k] = ds;
+          gy0[k] = sd;
+          gz0[k] = -ss;
         }
-      // u of plane q + 1 (same set as plane q - 1), used two iterations on
-      if (q + 1 >= z0 - 1 && q + 1 <= z1) fetch_u(Other{}, q + 1);
     }
     if (q >= z0 + 1) {
       // records V(q - 2): destination q - 3 completes
       const Rec<C>* t = tv[q & 1];
-      Rec<C> r[3][3];
+      C vx[3][3], vy[3][3], vz[3][3], ph[3][3];
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-        for (int dx = 0; dx < 3; ++dx) r[dy][dx] = t[(wy + dy) * VX + lane + dx];
-      const C own = r[1][1].phi;
-      C dvu = 0, lu = 0, dvc = 0, lc = 0, dvd = 0, ld = 0;
-#pragma unroll
-      for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-          const Rec<C>& n = r[dy + 1][dx + 1];
-          C cv = 0;
-          if (dx) cv += C(dx) * n.vx;
-          if (dy) cv += C(dy) * n.vy;
-          const C ku = C(k27(dx, dy, 1));
-          dvu += ku * (cv - n.vz);
-          dvd += ku * (cv + n.vz);
-          lu += ku * (n.phi - own);
-          ld += ku * (n.phi - pm);
-          if (dx || dy) {
-            const C kc = C(k27(dx, dy, 0));
-            dvc += kc * cv;
-            lc += kc * (n.phi - own);
-          }
+        for (int dx = 0; dx < 3; ++dx) {
+          const Rec<C> n = t[(wy + dy) * VX + lane + dx];
+          vx[dy][dx] = n.vx;
+          vy[dy][dx] = n.vy;
+          vz[dy][dx] = n.vz;
+          ph[dy][dx] = n.phi;
         }
+      const C own = ph[1][1];
+      // sum over the window of k1 k1 (c . V) in-plane (a) and of k1 k1 v_z
+      // (bz); the destination at dz = -1 (p + 1 seen from here) takes
+      // a - bz, at dz = +1 a + bz, the own plane 4 a; Laplacian sums
+      // relative to own (lu), and to pm for the destination at dz = +1
+      C ss, ds, sd;
+      window_sums(vx, ss, ds, sd);
+      const C ax = ds;
+      window_sums(vy, ss, ds, sd);
+      const C a = ax + sd;
+      window_sums(vz, ss, ds, sd);
+      const C bz = ss;
+      const C dvu = a - bz, dvd = a + bz, dvc = C(4) * a;
+      const C lu = window_lap(ph, own);
+      const C ld = lu + C(KZ) * (own - pm), lc = C(4) * lu;
       const int d = q - 3;
       if (mine && d >= z0 && d < z1)
         out[static_cast<int64_t>(d) * plane + static_cast<int64_t>(y) * nx + x] =
@@ -279,27 +291,42 @@ __global__ void __launch_bounds__(64 * kUpdRows) phase_kernel(
   };
   // phi planes z0 - 2 .. z1 + 1 give V(z0 - 1) .. V(z1), which give phi'(z0)
   // .. phi'(z1 - 1)
-  fetch_phi(I0{}, z0 - 2);
-  fetch_phi(I1{}, z0 - 1);
-  for (int q = z0 - 2; q <= z1 + 2; q += 2) {
-    body(q, I0{});
-    if (q + 1 <= z1 + 2) body(q + 1, I1{});
+  using B0 = std::integral_constant<int, 0>;
+  using B1 = std::integral_constant<int, 1>;
+  load_group(B0{}, z0 - 2);
+  // whole pairs of groups; iterations past z1 + 2 store nothing
+  for (int q = z0 - 2; q <= z1 + 2; q += 2 * G) {
+    load_group(B1{}, q + G);
+    static_for<G>([&](auto I) { body(q + decltype(I)::value, B0{}, I); });
+    load_group(B0{}, q + 2 * G);
+    static_for<G>([&](auto I) { body(q + G + decltype(I)::value, B1{}, I); });
   }
 }
 
 // Output of the force pass at one site: F = mu grad(phi) + rho(phi) g, plus
 // (contrast) the pressure and viscous terms - p* cs^2 grad(rho)
 // - (nu omega / cs^2) (a2 - u u) . grad(rho), with p*, u, a2 of the state at
-// the previous time level
+// the previous time level.  The state values a site needs are loaded ahead
+// (prefetch) and handed back with its derivatives.
 template <int ST, bool CONTRAST>
 struct ForceEmit {
   using S = Storage<ST>;
   using C = typename S::C;
+  struct Pre {
+    C m[CONTRAST ? 10 : 1];
+  };
   const typename S::T* st;
   C* F;
   int64_t N;
   PhaseArgs pa;
-  __device__ __forceinline__ void operator()(int64_t s, C p, const C g[3], C l) const {
+  __device__ __forceinline__ void prefetch(int64_t s, Pre& pre) const {
+    if constexpr (CONTRAST) {
+#pragma unroll
+      for (int k = 0; k < 10; ++k) pre.m[k] = S::load(st + k * N, s, pa.scale[k]);
+    }
+  }
+  __device__ __forceinline__ void operator()(int64_t s, C p, const C g[3], C l,
+                                             const Pre& pre) const {
     const C beta = static_cast<C>(pa.beta), kappa = static_cast<C>(pa.kappa);
     const C rl = static_cast<C>(pa.rho_l), dr = static_cast<C>(pa.rho_h - pa.rho_l);
     const C mu = C(4) * beta * p * (p - C(1)) * (p - C(0.5)) - kappa * l;
@@ -311,7 +338,7 @@ struct ForceEmit {
       const C nl = static_cast<C>(pa.nu_l), dn = static_cast<C>(pa.nu_h - pa.nu_l);
       C m[10];
 #pragma unroll
-      for (int k = 0; k < 10; ++k) m[k] = S::load(st + k * N, s, pa.scale[k]);
+      for (int k = 0; k < 10; ++k) m[k] = pre.m[k];
       // the non-equilibrium part a2 - u u (16-bit storage keeps it directly)
       if constexpr (!S::kNeq) {
 #pragma unroll
@@ -334,8 +361,11 @@ struct ForceEmit {
 };
 
 // grad(phi) and lap(phi) at every site, handed to an output functor: the
-// same tiles, z-march, staging and 2.5-D accumulation as the phase update,
-// on the scalar phi (a y wall's ghost is the mirror value)
+// same tiles, staging and 2.5-D accumulation as the phase update, on the
+// scalar phi (a y wall's ghost is the mirror value).  Iteration p stages
+// plane p and completes destination p - 1.  phi and the functor's per-site
+// values are loaded in groups into two register banks, as in the phase
+// update.
 template <typename C, class Emit>
 __global__ void __launch_bounds__(64 * kUpdRows) grad_march_kernel(const C* __restrict__ phi,
                                                                    int nx, int ny, int nz,
@@ -347,6 +377,7 @@ __global__ void __launch_bounds__(64 * kUpdRows) grad_march_kernel(const C* __re
   constexpr int NE = RY * RX;
   constexpr int PER = (NE + NT - 1) / NT;
   constexpr int KZ = 16 + 4 * 4 + 4 * 1;  // sum of k over the 9 sites of an adjacent plane
+  constexpr int G = kGroup;
   __shared__ C t[2][RY][RX];
   const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
   int b = static_cast<int>(blockIdx.x);
@@ -367,65 +398,60 @@ __global__ void __launch_bounds__(64 * kUpdRows) grad_march_kernel(const C* __re
     const int ry = act[k] ? e / RX : 0, rx = act[k] ? e - ry * RX : 0;
     const int xw = pmod(x0 + rx - 1, nx), yr = y0 + ry - 1;
     const int yw = walls_y ? clampi(yr, 0, ny - 1) : pmod(yr, ny);
-    off[k] = static_cast<int64_t>(yw) * nx + xw;
+    off[k] = act[k] ? static_cast<int64_t>(yw) * nx + xw : 0;
     pos[k] = ry * RX + rx;
   }
-  C r[PER];
-  auto fetch = [&](int z) {
-    const int64_t zb = static_cast<int64_t>(wrap(z, nz)) * plane;
-#pragma unroll
-    for (int k = 0; k < PER; ++k)
-      if (act[k]) r[k] = phi[zb + off[k]];
-  };
-  auto put = [&](int z) {
-    C* dst = &t[z & 1][0][0];
-#pragma unroll
-    for (int k = 0; k < PER; ++k)
-      if (act[k]) dst[pos[k]] = r[k];
-  };
   const int x = x0 + lane, y = y0 + wy;
   const bool mine = x < nx && y < ny;
+  // the functor's values of a thread without a site are read at offset 0
+  const int64_t own_off = mine ? static_cast<int64_t>(y) * nx + x : 0;
+  // slot i of a group starting at plane ps: phi of plane ps + i and the
+  // functor's values of destination ps + i - 1
+  C r[2][G][PER];
+  typename Emit::Pre pre[2][G];
+  auto load_group = [&](auto B, int ps) {
+    constexpr int b = decltype(B)::value;
+    static_for<G>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      const int64_t zb = static_cast<int64_t>(pmod(min(ps + i, z1), nz)) * plane;
+#pragma unroll
+      for (int k = 0; k < PER; ++k) r[b][i][k] = phi[zb + off[k]];
+      emit.prefetch(static_cast<int64_t>(clampi(ps + i - 1, z0, z1 - 1)) * plane + own_off,
+                    pre[b][i]);
+    });
+  };
   // destination p - 1 (sums and phi_0) and p (sums from plane p - 1, the
   // Laplacian relative to ref0)
   C gxm = 0, gym = 0, gzm = 0, lm = 0, pm = 0;
   C gx0 = 0, gy0 = 0, gz0 = 0, l0 = 0, ref0 = 0;
-  fetch(z0 - 1);
-  for (int p = z0 - 1; p <= z1; ++p) {
-    put(p);
+  auto body = [&](int p, auto B, auto I) {
+    constexpr int b = decltype(B)::value, i = decltype(I)::value;
+    {
+      C* dst = &t[p & 1][0][0];
+#pragma unroll
+      for (int k = 0; k < PER; ++k)
+        if (act[k]) dst[pos[k]] = r[b][i][k];
+    }
     __syncthreads();
-    if (p < z1) fetch(p + 1);
     C q[3][3];
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
       for (int dx = 0; dx < 3; ++dx) q[dy][dx] = t[p & 1][wy + dy][lane + dx];
     const C own = q[1][1];
-    // sums over this plane's 3 x 3 sites with the weights of an adjacent
-    // plane (ku) and of the own plane (kc, centre excluded)
-    C axu = 0, ayu = 0, azu = 0, lu = 0, ld = 0, axc = 0, ayc = 0, lc = 0;
-#pragma unroll
-    for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) {
-        const C n = q[dy + 1][dx + 1];
-        const C ku = C(k27(dx, dy, 1));
-        if (dx) axu += C(dx) * ku * n;
-        if (dy) ayu += C(dy) * ku * n;
-        azu += ku * n;
-        lu += ku * (n - own);
-        ld += ku * (n - pm);
-        if (dx || dy) {
-          const C kc = C(k27(dx, dy, 0));
-          if (dx) axc += C(dx) * kc * n;
-          if (dy) ayc += C(dy) * kc * n;
-          lc += kc * (n - own);
-        }
-      }
+    // this plane's separable sums with the weights of an adjacent plane; the
+    // own plane's weights are 4 times those (centre excluded from the
+    // Laplacian, where its term is zero)
+    C azu, axu, ayu;
+    window_sums(q, azu, axu, ayu);
+    const C lu = window_lap(q, own);
+    const C ld = lu + C(KZ) * (own - pm);
+    const C axc = C(4) * axu, ayc = C(4) * ayu, lc = C(4) * lu;
     // destination p - 1 is complete: this plane is at dz = +1 from it
     if (mine && p - 1 >= z0 && p - 1 < z1) {
       const C g[3] = {div_by<72>(gxm + axu), div_by<72>(gym + ayu), div_by<72>(gzm + azu)};
-      emit(static_cast<int64_t>(p - 1) * plane + static_cast<int64_t>(y) * nx + x, pm, g,
-           div_by<36>(lm + ld));
+      emit(static_cast<int64_t>(p - 1) * plane + own_off, pm, g, div_by<36>(lm + ld),
+           pre[b][i]);
     }
     // destination p: plane p - 1 (at dz = -1) plus this plane
     gxm = gx0 + axc;
@@ -439,25 +465,54 @@ __global__ void __launch_bounds__(64 * kUpdRows) grad_march_kernel(const C* __re
     gz0 = -azu;
     l0 = lu;
     ref0 = own;
+  };
+  using B0 = std::integral_constant<int, 0>;
+  using B1 = std::integral_constant<int, 1>;
+  load_group(B0{}, z0 - 1);
+  // whole pairs of groups; iterations past z1 emit nothing
+  for (int p = z0 - 1; p <= z1; p += 2 * G) {
+    load_group(B1{}, p + G);
+    static_for<G>([&](auto I) { body(p + decltype(I)::value, B0{}, I); });
+    load_group(B0{}, p + 2 * G);
+    static_for<G>([&](auto I) { body(p + G + decltype(I)::value, B1{}, I); });
   }
 }
 
-// tiles and z-chunks of the staged passes: 64 x kUpdRows columns, chunks of
-// >= 8 planes for about 512 workgroups
+// tiles and z-chunks of the staged passes: 64 x kUpdRows columns, z-chunks of
+// >= 8 planes, about as many workgroups as the device holds at once
+// (`target`), so that each CU runs as many marches as fit and they share
+// the memory latency
 struct MarchGeom {
   int tiles_x, tiles_y, zchunk, blocks;
 };
-MarchGeom march_geom(int nx, int ny, int nz) {
+MarchGeom march_geom(int nx, int ny, int nz, int target) {
   MarchGeom m;
   m.tiles_x = (nx + 63) / 64;
   m.tiles_y = (ny + kUpdRows - 1) / kUpdRows;
   const int cols = m.tiles_x * m.tiles_y;
-  int nch = (512 + cols - 1) / cols;
+  int nch = (target + cols - 1) / cols;
   const int maxc = nz >= 8 ? nz / 8 : 1;
   nch = nch < 1 ? 1 : (nch > maxc ? maxc : nch);
   m.zchunk = (nz + nch - 1) / nch;
   m.blocks = cols * ((nz + m.zchunk - 1) / m.zchunk);
   return m;
+}
+
+// workgroups of 64 x kUpdRows threads of `kernel` resident on the current
+// device at once (compute units x blocks per unit); 512 if the runtime does
+// not say
+template <class K>
+int resident_blocks(K kernel) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(kernel),
+                                                   64 * kUpdRows, 0) != hipSuccess ||
+      cus < 1 || per < 1) {
+    (void)hipGetLastError();
+    return 512;
+  }
+  return cus * per;
 }
 
 int phase_grid(int64_t N) {
@@ -469,7 +524,7 @@ template <int ST>
 hipError_t phase_step_st(const PhaseArgs& a, hipStream_t s) {
   using C = typename Storage<ST>::C;
   using T = typename Storage<ST>::T;
-  const MarchGeom m = march_geom(a.nx, a.ny, a.nz);
+  const MarchGeom m = march_geom(a.nx, a.ny, a.nz, resident_blocks(phase_kernel<ST>));
   hipLaunchKernelGGL((phase_kernel<ST>), dim3(m.blocks), dim3(64 * kUpdRows), 0, s,
                      static_cast<const C*>(a.phi), static_cast<const T*>(a.state),
                      static_cast<C*>(a.phi_out), a.nx, a.ny, a.nz, a.N, static_cast<C>(a.D),
@@ -495,19 +550,20 @@ template <int ST>
 hipError_t force_st(const PhaseArgs& a, hipStream_t s) {
   using C = typename Storage<ST>::C;
   using T = typename Storage<ST>::T;
-  const MarchGeom m = march_geom(a.nx, a.ny, a.nz);
   const C* phi = static_cast<const C*>(a.phi_out);
   const T* st = static_cast<const T*>(a.state);
+  auto launch = [&](auto contrast) {
+    using E = ForceEmit<ST, decltype(contrast)::value>;
+    const auto kernel = grad_march_kernel<C, E>;
+    const MarchGeom m = march_geom(a.nx, a.ny, a.nz, resident_blocks(kernel));
+    hipLaunchKernelGGL(kernel, dim3(m.blocks), dim3(64 * kUpdRows), 0, s, phi, a.nx, a.ny, a.nz,
+                       m.tiles_x, m.tiles_y, m.zchunk, a.walls_y != 0,
+                       E{st, static_cast<C*>(a.F), a.N, a});
+  };
   if (a.contrast)
-    hipLaunchKernelGGL((grad_march_kernel<C, ForceEmit<ST, true>>), dim3(m.blocks),
-                       dim3(64 * kUpdRows), 0, s, phi, a.nx, a.ny, a.nz, m.tiles_x, m.tiles_y,
-                       m.zchunk, a.walls_y != 0,
-                       ForceEmit<ST, true>{st, static_cast<C*>(a.F), a.N, a});
+    launch(std::true_type{});
   else
-    hipLaunchKernelGGL((grad_march_kernel<C, ForceEmit<ST, false>>), dim3(m.blocks),
-                       dim3(64 * kUpdRows), 0, s, phi, a.nx, a.ny, a.nz, m.tiles_x, m.tiles_y,
-                       m.zchunk, a.walls_y != 0,
-                       ForceEmit<ST, false>{st, static_cast<C*>(a.F), a.N, a});
+    launch(std::false_type{});
   return hipGetLastError();
 }
 }  // namespace
