@@ -201,8 +201,8 @@ typedef struct lbfast_phase_params {
 } lbfast_phase_params;
 
 /* Switch the handle to the two-component variant.  The library allocates
- * (and frees at destroy) 12 x N values of the compute type: phi and F for two
- * time levels, and the phase flux.  phi starts at 0. */
+ * (and frees at destroy) 8 x N values of the compute type: phi and F (three
+ * planes) for two time levels.  phi starts at 0. */
 int lbfast_enable_two_phase(lbfast_t h, const lbfast_phase_params* pp);
 /* Copy the phase field (N values, dtype LBF_F64 or LBF_F32, host or device)
  * in or out.  set also computes the force of the current time level, from
