@@ -24,6 +24,8 @@
 // the force from phi(t+1).  Algorithmic traffic at FP32: the phase update
 // 20 B per lattice update (phi, u in; phi out), the force 16 B (phi in, F
 // out), against the fused step's 104.
+#include <atomic>
+
 #include "internal.hpp"
 #include "lattice.hpp"
 
@@ -498,20 +500,32 @@ MarchGeom march_geom(int nx, int ny, int nz, int target) {
   return m;
 }
 
-// workgroups of 64 x kUpdRows threads of `kernel` resident on the current
+// workgroups of 64 x kUpdRows threads of kernel K resident on the current
 // device at once (compute units x blocks per unit); 512 if the runtime does
-// not say
-template <class K>
-int resident_blocks(K kernel) {
-  int dev = 0, cus = 0, per = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(kernel),
+// not say.  The answer depends only on the kernel and the device, so it is
+// asked once per device and kept.
+template <auto K>
+int resident_blocks() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 512;
+  }
+  const bool slot = dev >= 0 && dev < 64;
+  if (slot) {
+    const int c = cache[dev].load(std::memory_order_relaxed);
+    if (c > 0) return c;
+  }
+  int cus = 0, per = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(K),
                                                    64 * kUpdRows, 0) != hipSuccess ||
       cus < 1 || per < 1) {
     (void)hipGetLastError();
     return 512;
   }
+  if (slot) cache[dev].store(cus * per, std::memory_order_relaxed);
   return cus * per;
 }
 
@@ -524,7 +538,7 @@ template <int ST>
 hipError_t phase_step_st(const PhaseArgs& a, hipStream_t s) {
   using C = typename Storage<ST>::C;
   using T = typename Storage<ST>::T;
-  const MarchGeom m = march_geom(a.nx, a.ny, a.nz, resident_blocks(phase_kernel<ST>));
+  const MarchGeom m = march_geom(a.nx, a.ny, a.nz, resident_blocks<phase_kernel<ST>>());
   hipLaunchKernelGGL((phase_kernel<ST>), dim3(m.blocks), dim3(64 * kUpdRows), 0, s,
                      static_cast<const C*>(a.phi), static_cast<const T*>(a.state),
                      static_cast<C*>(a.phi_out), a.nx, a.ny, a.nz, a.N, static_cast<C>(a.D),
@@ -554,9 +568,8 @@ hipError_t force_st(const PhaseArgs& a, hipStream_t s) {
   const T* st = static_cast<const T*>(a.state);
   auto launch = [&](auto contrast) {
     using E = ForceEmit<ST, decltype(contrast)::value>;
-    const auto kernel = grad_march_kernel<C, E>;
-    const MarchGeom m = march_geom(a.nx, a.ny, a.nz, resident_blocks(kernel));
-    hipLaunchKernelGGL(kernel, dim3(m.blocks), dim3(64 * kUpdRows), 0, s, phi, a.nx, a.ny, a.nz,
+    const MarchGeom m = march_geom(a.nx, a.ny, a.nz, resident_blocks<grad_march_kernel<C, E>>());
+    hipLaunchKernelGGL((grad_march_kernel<C, E>), dim3(m.blocks), dim3(64 * kUpdRows), 0, s, phi, a.nx, a.ny, a.nz,
                        m.tiles_x, m.tiles_y, m.zchunk, a.walls_y != 0,
                        E{st, static_cast<C*>(a.F), a.N, a});
   };
