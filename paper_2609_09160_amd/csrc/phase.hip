@@ -265,10 +265,11 @@ __global__ void __launch_bounds__(64 * kUpdRows) phase_kernel(
           ph[dy][dx] = n.phi;
         }
       const C own = ph[1][1];
-      // sum over the window of k1 k1 (c . V) in-plane (a) and of k1 k1 v_z
-      // (bz); the destination at dz = -1 (p + 1 seen from here) takes
-      // a - bz, at dz = +1 a + bz, the own plane 4 a; Laplacian sums
-      // relative to own (lu), and to pm for the destination at dz = +1
+      // window sums of the records: a = sum k1 k1 (c_x v_x + c_y v_y) and
+      // bz = sum k1 k1 v_z.  The destination one plane up sees this plane at
+      // c_z = -1 and takes a - bz (dvu), the one below a + bz (dvd), this
+      // plane's own 4 a (dvc).  Laplacian sums relative to own (lu), and to
+      // pm, the phi of the destination below (ld).
       C ss, ds, sd;
       window_sums(vx, ss, ds, sd);
       const C ax = ds;
