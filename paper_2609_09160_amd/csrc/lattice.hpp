@@ -240,12 +240,13 @@ __device__ __forceinline__ uint16_t f32_to_f16_bits(float v) {
 __device__ __forceinline__ float f16_bits_to_f32(uint16_t q) {
   return static_cast<float>(__builtin_bit_cast(_Float16, q));
 }
-// bfloat16 (upper half of binary32), round to nearest even; NaN stays NaN
+// bfloat16 (upper half of binary32), round to nearest even; NaN stays NaN.
+// gfx950 converts in hardware (one instruction); checked bit for bit against
+// the integer rounding (add 0x7fff plus the kept part's lowest bit, keep the
+// upper half) on 2^24 values, including every exact tie and the special
+// values.
 __device__ __forceinline__ uint16_t f32_to_bf16_bits(float v) {
-  uint32_t u = __float_as_uint(v);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return static_cast<uint16_t>(u >> 16);
+  return __builtin_bit_cast(uint16_t, static_cast<__bf16>(v));
 }
 __device__ __forceinline__ float bf16_bits_to_f32(uint16_t q) {
   return __uint_as_float(static_cast<uint32_t>(q) << 16);
