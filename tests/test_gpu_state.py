@@ -69,6 +69,57 @@ def test_16bit_scaled_roundtrip(storage, bits):
     s.close()
 
 
+def _ties(storage, n):
+    """n binary32 values that lie exactly halfway between two neighbouring
+    16-bit values (kept parts alternately even and odd), over many exponents."""
+    i = np.arange(n, dtype=np.uint32)
+    if storage == "bf16s":
+        # exponents 100..139, 3 kept mantissa bits varying, dropped half = 0x8000
+        bits = ((100 + i % 40) << 23) | ((i // 40 % 8) << 16) | 0x8000
+        return bits.astype(np.uint32).view(np.float32)
+    # float16: 1.k... between k * 2^-10 and (k + 1) * 2^-10, times 2^e
+    k = (i % 64).astype(np.float64)
+    e = (i // 64 % 12).astype(np.float64) - 6.0
+    return ((1.0 + k * 2.0 ** -10 + 2.0 ** -11) * 2.0 ** e).astype(np.float32)
+
+
+@pytest.mark.parametrize("storage", ["f16s", "bf16s"])
+def test_16bit_encoding_bit_exact(storage):
+    """The stored words of the planes kept directly (p*, u) are v / s rounded to
+    nearest even, bit for bit.  The expected words come from numpy's float16
+    conversion for FP16 and from integer rounding of the binary32 pattern for
+    BF16, both independent of the kernel's conversion instruction.  The p*
+    plane holds exact ties at many exponents, where round-half-up or
+    truncation would differ."""
+    import torch
+    shape = (64, 32, 16)
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    m = inputs.random_state(shape, seed=21)
+    t = _ties(storage, 4096).astype(np.float64)
+    p = m[0].reshape(-1)
+    p[:t.size] = t
+    m[0] = p.reshape(nz, ny, nx)
+    s = _solver(shape, storage=storage, scale=[1.0] * 10)
+    s.set_moments(m)
+    assert np.array_equal(s.scales(), np.ones(10, dtype=np.float32))
+    ptr = s.state_ptr()
+    buf = [b for b in s._bufs if b.data_ptr() == ptr]
+    assert len(buf) == 1
+    words = buf[0][:10 * N * 2].cpu().numpy().view(np.uint16).reshape(10, N)
+    for k in range(4):
+        x = m[k].reshape(-1).astype(np.float32)
+        if storage == "f16s":
+            want = x.astype(np.float16).view(np.uint16)
+        else:
+            u = x.view(np.uint32).astype(np.uint64)
+            want = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+        bad = int((words[k] != want).sum())
+        say(f"{storage} plane {k}: {bad} of {N} words differ")
+        assert bad == 0
+    s.close()
+
+
 def test_zero_steps_and_determinism():
     shape = (70, 13, 9)
     m = inputs.random_state(shape, seed=3)
