@@ -141,6 +141,27 @@ int lbfast_sync(lbfast_t h);
  * Returns LBF_E_NONFINITE (out still written) if any sum is NaN/Inf. */
 int lbfast_reduce(lbfast_t h, double out[5]);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the sums of
+ * lbfast_reduce over any moment array, with no handle and no allocation.
+ *   state_dev  10 x n_sites values in the storage format `storage`
+ *              (LBF_F64, LBF_F32, LBF_F16S or LBF_BF16S), device memory, e.g.
+ *              lbfast_state_ptr() or a checkpoint slot; read only;
+ *   scale      the ten 16-bit storage scales (lbfast_get_scales), host array;
+ *              required for F16S/BF16S, ignored (may be NULL) otherwise;
+ *   out_dev    5 doubles of device memory, receives
+ *              [sum a0, sum a1x, sum a1y, sum a1z, 1/2 sum |a1|^2];
+ *   stream     hipStream_t of the current device (NULL = legacy stream).
+ * Asynchronous: the result is in out_dev once the stream reaches it; no
+ * synchronisation and no non-finite check (the caller inspects out_dev).
+ * The per-block partial sums live in a fixed 40 KiB device array of the
+ * library, one per GPU, held until the process ends; calls that overlap on one
+ * GPU (different streams or threads) race on it and must be serialised by the
+ * caller.  n_sites above 4e9 (the largest grid lbfast_create accepts) is
+ * rejected with LBF_E_ARG, as are NULL, misaligned or host pointers. */
+int lbfast_reduce_noalloc(const void* state_dev, int storage, int64_t n_sites,
+                          const float scale[10], double* out_dev, void* stream);
+
 /* Device pointer to the buffer holding the current state (flips every
  * step), for zero-copy reads; valid until the next step/destroy. */
 int lbfast_state_ptr(lbfast_t h, void** dev_ptr);

@@ -73,6 +73,7 @@ def load():
         "lbfast_step": ([vp, i64], i32),
         "lbfast_sync": ([vp], i32),
         "lbfast_reduce": ([vp, ctypes.POINTER(ctypes.c_double)], i32),
+        "lbfast_reduce_noalloc": ([vp, i32, i64, ctypes.POINTER(ctypes.c_float), vp, vp], i32),
         "lbfast_state_ptr": ([vp, ctypes.POINTER(vp)], i32),
         "lbfast_get_scales": ([vp, ctypes.POINTER(ctypes.c_float)], i32),
         "lbfast_set_launch": ([vp, i32, i32], i32),

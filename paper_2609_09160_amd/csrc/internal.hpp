@@ -7,6 +7,10 @@
 
 namespace lbf {
 
+// the calling thread's message for lbfast_last_error (lbfast.cpp)
+void clear_error();
+int set_error(int code, const char* msg);
+
 // Arguments of one fused step launch (by value into the kernel).
 struct StepArgs {
   const void* src;     // current moment buffer (10 planes)

@@ -34,6 +34,19 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
+}  // namespace
+
+// error reporting for entry points defined in other translation units
+namespace lbf {
+void clear_error() { g_err.clear(); }
+int set_error(int code, const char* msg) {
+  g_err = msg;
+  return code;
+}
+}  // namespace lbf
+
+namespace {
+
 int hip_fail(hipError_t e, const char* what) {
   return fail(LBF_E_DEVICE, "%s: %s (%d)", what, hipGetErrorString(e), static_cast<int>(e));
 }
