@@ -429,7 +429,12 @@ int oracle_run(int lat, int64_t nx, int64_t ny, int64_t nz, const int* bc, doubl
  *   F^nu = - (nu omega / cs^2) (a2 - u u) . grad(rho)   (the printed form is
  *         garbled; this is the viscous-stress term nu (grad u + grad u^T) .
  *         grad(rho) with the stress written through the non-equilibrium
- *         coefficient of Eq. (6)).
+ *         coefficient of Eq. (6): nu omega / cs^2 = 1 - omega/2, the stress
+ *         of the Guo scheme.  The paper's starred (pre-correction)
+ *         coefficient, taken with the pre-correction velocity, differs from
+ *         a2 - u u only by - F F / (4 rho^2), second order in the force and
+ *         left out: with it a2 - u u, a uniformly accelerated flow keeps
+ *         F^nu = 0 exactly, as it has no shear).
  * Spatial derivatives use the D3Q27-weighted stencils of section 2:
  *   grad_a Psi(x) = (1/cs^2) sum_i w_i Psi(x + c_i) c_ia,
  *   lap Psi(x)    = (2/cs^2) sum_{i != 0} w_i [Psi(x + c_i) - Psi(x)]
