@@ -8,12 +8,15 @@ launch).  Prints ONE JSON line: the main workload's MLUPS and HBM roofline
 fraction (with the calibrated counter traffic when it matches the kernel
 sources), the measured copy ceiling, energy per update, the D3Q27 / 16-bit /
 FP64 / D3Q27h (complete Hermite basis; bound by its arithmetic, not by HBM)
-variants, the discrete adjoint (192^3) and the two-component droplet
-(256^3, equal phases and with contrast), and the CPU oracle baseline.
+variants, the error of every non-FP64 form against FP64 after 1000 steps at
+the same size (with its bar: 1e-5 FP32, 1e-3 16-bit), the discrete adjoint
+(192^3, checkpoints every 50 steps) and the two-component droplet (256^3,
+equal phases and with contrast), and the CPU oracle baseline (D3Q19 and
+D3Q27, all host cores and one).
 
   python bench.py [--steps K] [--warmup W] [--lattice 19|27|27h]
                   [--storage f32|f64|f16s|bf16s] [--n 512] [--no-variants]
-                  [--no-adjoint] [--no-cpu-baseline] [--copy-probe]
+                  [--no-adjoint] [--no-accuracy] [--no-cpu-baseline] [--copy-probe]
 """
 import argparse
 import hashlib
@@ -264,10 +267,10 @@ def _adjoint_times(s, n, steps, every, reps):
 def run_adjoint(n=192, steps=500, reps=2):
     """Adjoint workload: D3Q19 FP32 n^3 periodic, tau = 0.8, from rest, per-site
     force std 1e-6 (seed 160), J = 1/2 sum |u(T)|^2.  Adjoint MLUPS = sites *
-    steps / backward time.  Headline: every state kept (checkpoint interval 1,
-    steps x 283 MB of HBM at 192^3), so the backward pass runs one adjoint step
-    per time step; also reported with checkpoints every 50 steps, where each
-    segment is recomputed before it is swept."""
+    steps / backward time.  Headline: checkpoints every 50 steps, each segment
+    recomputed before it is swept; also reported with every state kept
+    (checkpoint interval 1, steps x 283 MB of HBM at 192^3), where the backward
+    pass runs one adjoint step per time step."""
     import torch
     from paper_2609_09160_amd import Solver, inputs
     shape = (n, n, n)
@@ -283,16 +286,17 @@ def run_adjoint(n=192, steps=500, reps=2):
     torch.cuda.empty_cache()
     adj_step_ms = (b50 - f50) / steps  # backward minus one recomputation pass
     adj_gbs = ADJ_BYTES_PER_LUP * sites / (adj_step_ms * 1e-3) / 1e9
-    return {"mlups": round(sites * steps / (b1 * 1e-3) / 1e6, 1),
+    return {"mlups": round(sites * steps / (b50 * 1e-3) / 1e6, 1),
             "workload": f"D3Q19 FP32 {n}^3 periodic, tau=0.8, from rest, per-site force "
-                        f"std 1e-6 (seed 160), J=1/2 sum|u({steps})|^2, every state kept "
-                        f"({ckpt_gb:.1f} GB of checkpoints)",
-            "ms_backward": round(b1, 3), "ms_forward_checkpointed": round(f1, 3),
-            "backward_bytes_per_lup": ADJ_BYTES_PER_LUP,
-            "checkpoint_every_50": {
-                "mlups": round(sites * steps / (b50 * 1e-3) / 1e6, 1),
-                "ms_backward": round(b50, 3), "ms_forward_checkpointed": round(f50, 3),
-                "backward_bytes_per_lup": ADJ_BYTES_PER_LUP + FWD_F_BYTES_PER_LUP},
+                        f"std 1e-6 (seed 160), J=1/2 sum|u({steps})|^2, checkpoint every 50 "
+                        "steps (backward pass recomputes each segment, then sweeps it)",
+            "ms_backward": round(b50, 3), "ms_forward_checkpointed": round(f50, 3),
+            "backward_bytes_per_lup": ADJ_BYTES_PER_LUP + FWD_F_BYTES_PER_LUP,
+            "every_state_kept": {
+                "mlups": round(sites * steps / (b1 * 1e-3) / 1e6, 1),
+                "ms_backward": round(b1, 3), "ms_forward_checkpointed": round(f1, 3),
+                "backward_bytes_per_lup": ADJ_BYTES_PER_LUP,
+                "checkpoint_GB": round(ckpt_gb, 1)},
             "adjoint_step_ms": round(adj_step_ms, 5),
             "adjoint_step_bytes_per_lup": ADJ_BYTES_PER_LUP,
             "adjoint_step_GBs": round(adj_gbs, 1),
@@ -344,29 +348,88 @@ def run_two_phase(n=256, steps=100, warmup=10, storage="f32", contrast=False):
             "algorithmic_GBs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
-def cpu_baseline(lattice, budget_s=20.0):
-    """The FP64 CPU oracle on the host cores, bounded sample of the workload."""
+ACCURACY_BARS = {"f32": 1e-5, "f16s": 1e-3, "bf16s": 1e-3}  # u rel L2 after 1000 steps
+
+
+def accuracy_vs_fp64(n, lattices, forms, steps=1000):
+    """Relative L2 error of u after `steps` of the n^3 solenoidal workload for
+    each (lattice, storage) of `forms`, against the same run in FP64 on the GPU
+    (the FP64 path is element-wise parity-checked against the FP64 CPU
+    oracle)."""
+    import torch
+    from paper_2609_09160_amd import Solver
+    m0 = make_input((n, n, n), "cuda")
+    out = {}
+    for lat in lattices:
+        s = Solver((n, n, n), 0.6, lattice=lat, storage="f64")
+        s.set_moments(m0)
+        s.step(steps)
+        ref = s.moments()[1:4].clone()
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        rn = float(torch.linalg.vector_norm(ref))
+        for st in [st for la, st in forms if la == lat]:
+            s = Solver((n, n, n), 0.6, lattice=lat, storage=st)
+            s.set_moments(m0)
+            s.step(steps)
+            buf = torch.empty((10, n, n, n), dtype=torch.float32, device="cuda")
+            s.moments(out=buf)
+            s.close()
+            del s
+            e = float(torch.linalg.vector_norm(buf[1:4].double() - ref)) / rn
+            del buf
+            torch.cuda.empty_cache()
+            out[(lat, st)] = e
+        del ref
+        torch.cuda.empty_cache()
+    del m0
+    torch.cuda.empty_cache()
+    return out
+
+
+def _time_oracle(lattice, nthreads, budget_s):
+    """MLUPS of the FP64 CPU oracle on 128^3 of the solenoidal field with
+    `nthreads` OpenMP threads (None: all the process may use), about
+    budget_s of timed stepping after one untimed step."""
     import numpy as np
     import oracle
     from paper_2609_09160_amd import inputs
     n = 128
     shape = (n, n, n)
-    m0 = inputs.solenoidal_field(shape)
-    o = oracle.PopulationOracle(lattice, shape, 0.6)
-    o.set_moments(m0)
-    o.step(1)  # warm-up
-    t0 = time.perf_counter()
-    o.step(1)
-    one = time.perf_counter() - t0
-    k = max(1, min(1000, int(budget_s / max(one, 1e-3))))
-    t0 = time.perf_counter()
-    o.step(k)
-    dt = time.perf_counter() - t0
-    assert np.isfinite(o.f).all()
-    return {"value": round(n ** 3 * k / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.threads(),
+    default = oracle.threads()
+    oracle.set_threads(nthreads or default)
+    try:
+        used = oracle.threads()
+        o = oracle.PopulationOracle(lattice, shape, 0.6)
+        o.set_moments(inputs.solenoidal_field(shape))
+        o.step(1)  # warm-up
+        t0 = time.perf_counter()
+        o.step(1)
+        one = time.perf_counter() - t0
+        k = max(1, min(1000, int(budget_s / max(one, 1e-3))))
+        t0 = time.perf_counter()
+        o.step(k)
+        dt = time.perf_counter() - t0
+        assert np.isfinite(o.f).all()
+    finally:
+        oracle.set_threads(default)
+    return {"value": round(n ** 3 * k / dt / 1e6, 3), "unit": "MLUPS", "cores": used,
             "kind": "oracle",
             "sample": f"D3Q{lattice} FP64 population oracle, {n}^3 of the same solenoidal field, "
                       f"tau=0.6, {k} timed steps after 2 untimed ({dt:.1f} s)"}
+
+
+def cpu_baseline(lattice, budget_s=6.0):
+    """The FP64 CPU oracle on the host cores (all of them, and one), bounded
+    samples of the workload, for the benchmarked lattice and for the other
+    second-order set.  The headline is the benchmarked lattice on all cores."""
+    other = 27 if lattice == 19 else 19
+    out = _time_oracle(lattice, None, budget_s)
+    out["one_thread"] = _time_oracle(lattice, 1, budget_s)
+    out[f"d3q{other}"] = _time_oracle(other, None, budget_s)
+    out[f"d3q{other}"]["one_thread"] = _time_oracle(other, 1, budget_s)
+    return out
 
 
 def main():
@@ -381,6 +444,8 @@ def main():
                     help="skip the short runs of D3Q27, FP64 and 16-bit storage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the 1000-step error of each storage form against FP64")
     ap.add_argument("--tile-rows", type=int, default=0, help="launch override (0 = default)")
     ap.add_argument("--z-chunk", type=int, default=0, help="launch override (0 = default)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -455,7 +520,7 @@ def main():
     if not args.no_variants:
         var = {}
         for lat, st in ((27, "f32"), (19, "f16s"), (19, "bf16s"), (27, "f16s"), (19, "f64"),
-                        ("27h", "f32"), ("27h", "f64")):
+                        ("27h", "f32"), ("27h", "f16s"), ("27h", "f64")):
             if (lat, st) == (args.lattice, args.storage):
                 continue
             r = run_gpu(n, lat, st, max(20, args.steps // 4), 5)
@@ -464,6 +529,24 @@ def main():
                                      "algorithmic_GBs": round(r["algorithmic_GBs"], 1),
                                      "hbm_frac": round(r["hbm_frac"], 4)}
         out["variants"] = var
+    if not args.no_accuracy and args.storage != "f64":
+        # every benchmarked form that is not FP64 itself, at the benchmark's size
+        forms = [(args.lattice, args.storage)]
+        if not args.no_variants:
+            forms += [(lat, st) for lat, st in ((27, "f32"), (19, "f16s"), (19, "bf16s"),
+                                               (27, "f16s"), ("27h", "f32"), ("27h", "f16s"))
+                      if (lat, st) != (args.lattice, args.storage)]
+        lats = list(dict.fromkeys(lat for lat, _ in forms))
+        errs = accuracy_vs_fp64(n, lats, forms)
+        for (lat, st), e in errs.items():
+            entry = {"u_rel_l2_vs_fp64": float(f"{e:.3g}"), "steps": 1000,
+                     "bar": ACCURACY_BARS[st], "meets_bar": bool(e <= ACCURACY_BARS[st])}
+            if (lat, st) == (args.lattice, args.storage):
+                entry["reference"] = ("the same run in FP64 on the GPU (element-wise "
+                                      "parity-checked against the FP64 CPU oracle)")
+                out["accuracy"] = entry
+            else:
+                var[f"d3q{lat}_{st}"]["accuracy"] = entry
     if not args.no_adjoint:
         out["adjoint"] = run_adjoint()
     if not args.no_variants:

@@ -96,9 +96,15 @@ typedef struct lbfast_params {
                            ignored while a force field is set */
   float scale[10];      /* 16-bit storage only: power-of-two scale per moment
                            plane; 0 = choose at the first set_moments as the
-                           power of two that maps 2*max|v| (v the plane's
-                           total value) just below 2^15; a state at rest has
-                           no magnitude to go by: pass scales explicitly */
+                           power of two that maps max|v| (v the plane's total
+                           value) just below 2^10.  The scales then stay fixed:
+                           FP16 storage overflows once a plane grows beyond
+                           64 times its magnitude at that set_moments (a
+                           channel driven from noise or from rest, a flow
+                           spun up by a force), which lbfast_reduce reports
+                           as LBF_E_NONFINITE; pass scales sized for the
+                           largest expected values in such runs, and for a
+                           state at rest, which has no magnitude to go by */
   int32_t reserved[8];  /* must be zero */
 } lbfast_params;
 
@@ -109,7 +115,11 @@ int lbfast_abi_version(void);
  * params.  The memory model of section 3: M = N * n_fields * b. */
 size_t lbfast_buffer_bytes(const lbfast_params* p);
 
-/* Create a solver.  `stream` is a hipStream_t (NULL = legacy default stream).
+/* Create a solver for the problem the paper states in section 2: a lattice
+ * of nx x ny x nz sites, a velocity set, the relaxation time of the
+ * collision (Eq. (3), nu = cs^2 (tau - 1/2)) and a body force (Eq. (9)),
+ * with the two ten-field flip/flop state buffers of section 3
+ * ("Implementation").  `stream` is a hipStream_t (NULL = legacy default stream).
  * buf0/buf1: two device buffers of lbfast_buffer_bytes(p) bytes, 256-byte
  * aligned, borrowed (caller frees after destroy); pass both NULL to have the
  * library allocate and own them.  The state is zero (rest) after create. */
@@ -117,8 +127,10 @@ int lbfast_create(const lbfast_params* p, void* stream, void* buf0, void* buf1,
                   lbfast_t* out);
 int lbfast_destroy(lbfast_t h);
 
-/* Copy a moment array (10 x N, dtype LBF_F64 or LBF_F32, physical values)
- * into / out of the current state.  on_device: 1 = device pointer, 0 = host.
+/* Copy a moment array (10 x N, dtype LBF_F64 or LBF_F32, physical values):
+ * the Hermite coefficients p*, u, a2 of Eq. (6) that section 3 stores per
+ * site, as reported after the correction of Eq. (8), into / out of the
+ * current state.  on_device: 1 = device pointer, 0 = host.
  * set converts to the storage type (round to nearest even); get converts
  * from it.  get synchronises the stream. */
 int lbfast_set_moments(lbfast_t h, const void* m, int dtype, int on_device);
@@ -137,7 +149,10 @@ int lbfast_step(lbfast_t h, int64_t n);
 int lbfast_sync(lbfast_t h);
 
 /* Deterministic FP64 sums over the current state (synchronising):
- * out = [sum a0, sum a1x, sum a1y, sum a1z, 1/2 sum |a1|^2].
+ * out = [sum a0, sum a1x, sum a1y, sum a1z, 1/2 sum |a1|^2]: the totals the
+ * step conserves (the zeroth and first Hermite coefficients, Eqs. (5) and
+ * (8): sum p* exactly, sum u up to the applied force) and the kinetic energy
+ * whose decay the Taylor-Green validation of section 4 fits.
  * Returns LBF_E_NONFINITE (out still written) if any sum is NaN/Inf. */
 int lbfast_reduce(lbfast_t h, double out[5]);
 
@@ -266,20 +281,6 @@ int lbfast_forward_checkpointed(lbfast_t h, int64_t nsteps, int64_t every, void*
 size_t lbfast_adjoint_work_bytes(lbfast_t h, int64_t every);
 int lbfast_adjoint(lbfast_t h, int64_t nsteps, int64_t every, const void* ckpt_dev,
                    const void* lambda_T_dev, void* gF_dev, void* lambda0_dev, void* work_dev);
-
-/* Measurement utility, not part of the method: copy `nplanes` planes of `n`
- * floats from src to dst (device pointers, n * 4 < 2^32) on `stream`, using
- * the same memory instruction forms as the step (dword buffer loads,
- * non-temporal dword buffer stores).  A copy of known size, used to calibrate
- * hardware traffic counters against the step. */
-int lbfast_stream_probe(const void* src, void* dst, int64_t n, int nplanes, void* stream);
-
-/* Measurement utility, not part of the method: copy n4 16-byte elements from
- * src to dst (device pointers, 16-byte aligned) on `stream` with one 16-byte
- * access per lane and non-temporal stores, the fastest copy form measured on
- * MI355X: the bandwidth ceiling of a stream that reads and writes equal
- * volumes, against which the step's achieved bandwidth is set. */
-int lbfast_copy_probe(const void* src, void* dst, int64_t n4, void* stream);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char* lbfast_last_error(void);

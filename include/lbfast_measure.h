@@ -1,0 +1,34 @@
+/*
+ * lbfast_measure.h -- measurement utilities of liblbfast.so.  They are not
+ * part of the method: copy kernels of known size, used to calibrate hardware
+ * traffic counters against the step and to measure the bandwidth ceiling
+ * the step is set against.  Same status codes and error reporting as
+ * lbfast.h.
+ */
+#ifndef LBFAST_MEASURE_H_
+#define LBFAST_MEASURE_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Measurement utility, not part of the method: copy `nplanes` planes of `n`
+ * floats from src to dst (device pointers, n * 4 < 2^32) on `stream`, using
+ * the same memory instruction forms as the step (dword buffer loads,
+ * non-temporal dword buffer stores).  A copy of known size, used to calibrate
+ * hardware traffic counters against the step. */
+int lbfast_stream_probe(const void* src, void* dst, int64_t n, int nplanes, void* stream);
+
+/* Measurement utility, not part of the method: copy n4 16-byte elements from
+ * src to dst (device pointers, 16-byte aligned) on `stream` with one 16-byte
+ * access per lane and non-temporal stores, the fastest copy form measured on
+ * MI355X: the bandwidth ceiling of a stream that reads and writes equal
+ * volumes, against which the step's achieved bandwidth is set. */
+int lbfast_copy_probe(const void* src, void* dst, int64_t n4, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBFAST_MEASURE_H_ */

@@ -89,6 +89,14 @@ def threads() -> int:
     return _load().oracle_threads()
 
 
+def set_threads(n: int) -> None:
+    """Use n OpenMP threads in the oracle's later loops."""
+    lib = _load()
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = None
+    lib.oracle_set_threads(int(n))
+
+
 def lattice_tables(Q):
     """(c[Q,3] int, w[Q] float64) of the oracle's velocity set."""
     lib = _load()

@@ -59,6 +59,15 @@ int oracle_threads(void) {
 #endif
 }
 
+/* Set the number of OpenMP threads for later parallel loops (n >= 1). */
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* Build the velocity set: enumerate {-1,0,1}^3, keep |c|^2 <= 2 for Q=19.
  * Returns Q, or -1 for an unknown Q. */
 #define D3Q27H 270

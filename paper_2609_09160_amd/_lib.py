@@ -10,6 +10,7 @@ import re
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbfast.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "lbfast.h")
+HEADERS = (HEADER, os.path.join(os.path.dirname(_HERE), "include", "lbfast_measure.h"))
 
 # constants mirrored from include/lbfast.h
 LBF_OK, LBF_E_ARG, LBF_E_UNSUPPORTED, LBF_E_NOMEM = 0, -1, -2, -3
@@ -103,8 +104,9 @@ def check(rc):
 
 
 def declared_functions():
-    """Names of the functions include/lbfast.h declares."""
-    text = open(HEADER).read()
+    """Names of the functions include/lbfast.h and include/lbfast_measure.h
+    declare."""
+    text = "".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(lbfast_[a-z0-9_]+)\s*\(", text)))
 

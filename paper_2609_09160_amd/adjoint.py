@@ -27,6 +27,11 @@ class LBFastAdjoint(torch.autograd.Function):
         solver.set_moments(m0.detach())
         ckpt = solver.forward_checkpointed(nsteps, every)
         mT = solver.moments(dtype=solver.compute_dtype)
+        # The backward pass recomputes segments with this force field: save
+        # it, so that later forward calls or set_force_field on the same
+        # solver do not change the gradient of this call (and an in-place
+        # change of F before backward raises, as for any saved tensor).
+        ctx.save_for_backward(F)
         ctx.solver, ctx.ckpt, ctx.nsteps, ctx.every = solver, ckpt, int(nsteps), int(every)
         ctx.F_dtype, ctx.m0_dtype = F.dtype, m0.dtype
         ctx.F_shape, ctx.m0_shape = F.shape, m0.shape
@@ -35,6 +40,8 @@ class LBFastAdjoint(torch.autograd.Function):
     @staticmethod
     @torch.autograd.function.once_differentiable
     def backward(ctx, g_mT):
+        (F,) = ctx.saved_tensors
+        ctx.solver.set_force_field(F.detach())
         gF, g0 = ctx.solver.adjoint(ctx.nsteps, ctx.every, ctx.ckpt, g_mT,
                                     want_m0=ctx.needs_input_grad[1])
         gF = gF.reshape(ctx.F_shape).to(ctx.F_dtype)

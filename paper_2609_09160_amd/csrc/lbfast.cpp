@@ -2,6 +2,7 @@
 // validation, buffer ownership, flip/flop bookkeeping (the paper's two
 // ten-field arrays, section 3), launch shape, conversions and reductions.
 #include "lbfast.h"
+#include "lbfast_measure.h"
 
 #include <hip/hip_runtime.h>
 
@@ -470,7 +471,10 @@ int lbfast_set_moments(lbfast_t h, const void* m, int dtype, int on_device) {
                          hipMemcpyHostToDevice, h->stream);
     return p;
   };
-  // automatic 16-bit scales: the power of two placing 2*max|v| just below 2^15
+  // automatic 16-bit scales: the power of two placing max|v| just below 2^10,
+  // which leaves a factor 64 of growth before FP16 overflows (65504); FP16
+  // keeps its relative precision down to 2^-14, far below any value that
+  // matters next to max|v|
   // (v: the plane's total value, the deviation planes included)
   if (!h->scales_fixed) {
     for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
@@ -496,8 +500,8 @@ int lbfast_set_moments(lbfast_t h, const void* m, int dtype, int on_device) {
         float sc = 1.0f;
         if (mx > 0.0f && std::isfinite(mx)) {
           int ex;
-          std::frexp(2.0f * mx, &ex);      // 2*mx in [2^(ex-1), 2^ex)
-          sc = std::ldexp(1.0f, ex - 15);  // 2*mx / sc < 2^15
+          std::frexp(mx, &ex);             // mx in [2^(ex-1), 2^ex)
+          sc = std::ldexp(1.0f, ex - 10);  // mx / sc < 2^10
         }
         h->scale[k] = sc;
         h->inv_scale[k] = 1.0f / sc;

@@ -250,6 +250,32 @@ def test_autograd_function_matches_direct_call():
     assert np.array_equal(m0.grad.cpu().numpy().reshape(10, N), g0)
 
 
+def test_autograd_two_forwards_on_one_solver():
+    """Two simulate calls on one solver, then the first call's backward: its
+    gradient uses the first call's force field (kept by the autograd node),
+    bit for bit the gradient of the same call on a fresh solver."""
+    import torch
+    from paper_2609_09160_amd import Solver
+    from paper_2609_09160_amd.adjoint import simulate
+    shape = (20, 18, 10)
+    nx, ny, nz = shape
+    m0 = torch.tensor(inputs.random_state(shape, seed=62).reshape(10, nz, ny, nx), device="cuda")
+    F1n = inputs.random_force(shape, seed=63, std=1e-4).reshape(3, nz, ny, nx)
+    F2n = inputs.random_force(shape, seed=64, std=3e-4).reshape(3, nz, ny, nx)
+    s = Solver(shape, 0.75, storage="f64")
+    F1 = torch.tensor(F1n, device="cuda", requires_grad=True)
+    F2 = torch.tensor(F2n, device="cuda", requires_grad=True)
+    J1 = 0.5 * (simulate(F1, m0, 0.75, 20, every=5, solver=s)[1:4] ** 2).sum()
+    J2 = 0.5 * (simulate(F2, m0, 0.75, 20, every=5, solver=s)[1:4] ** 2).sum()
+    J1.backward()
+    s.close()
+    F1f = torch.tensor(F1n, device="cuda", requires_grad=True)
+    Jf = 0.5 * (simulate(F1f, m0, 0.75, 20, every=5, storage="f64")[1:4] ** 2).sum()
+    Jf.backward()
+    assert float(J1) == float(Jf) and float(J2) != float(J1)
+    assert torch.equal(F1.grad, F1f.grad)
+
+
 def test_adjoint_argument_errors():
     """16-bit storage and the full-basis D3Q27h set have no adjoint; bad
     step counts are rejected on the host before any device work."""

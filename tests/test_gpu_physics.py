@@ -20,11 +20,14 @@ def _cuda():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
 
 
+@pytest.mark.parametrize("sites", [1, 2])
 @pytest.mark.parametrize("Q", [19, 27, "27h"])
 @pytest.mark.parametrize("storage,bound", [("f16s", 1e-3), ("bf16s", 1e-1)])
-def test_16bit_storage_accuracy(Q, storage, bound):
+def test_16bit_storage_accuracy(Q, storage, bound, sites):
     """16-bit scaled moment storage (FP32 arithmetic), 64^3 solenoidal workload,
-    tau = 0.6, 1000 steps: relative L2 error of u against the FP64 oracle.
+    tau = 0.6, 1000 steps: relative L2 error of u against the FP64 oracle, with
+    one and with two x-sites per lane (two is the form the 512^3 benchmark
+    runs; at 64^3 the default is one).
     FP16 (11-bit significand) meets the 1e-3 bar stated for the 16-bit form.
     BF16 (8-bit significand) cannot: u itself is re-rounded every step with
     unit roundoff 2^-9 ~ 2e-3, and the low-wavenumber part of that noise
@@ -32,10 +35,53 @@ def test_16bit_storage_accuracy(Q, storage, bound):
     reported and held to that derived order, 1e-1."""
     n = 64
     m0, want = solenoidal_oracle_1000(Q, n)
-    got = gpu_run((n, n, n), 0.6, m0, 1000, lattice=Q, storage=storage)
+    got = gpu_run((n, n, n), 0.6, m0, 1000, lattice=Q, storage=storage, launch=(0, 0, sites))
     e = u_rel_l2(got, want)
-    say(f"{storage} Q{Q}: u rel L2 after 1000 steps = {e:.3e}")
+    say(f"{storage} Q{Q} {sites} site(s) per lane: u rel L2 after 1000 steps = {e:.3e}")
     assert e <= bound
+
+
+@pytest.mark.parametrize("Q", [19, 27, "27h"])
+def test_storage_forms_512_vs_fp64(Q):
+    """Every storage form at the benchmark's size and launch shape: the 512^3
+    solenoidal workload (tau = 0.6), 1000 steps, relative L2 error of u
+    against the GPU's FP64 path (itself element-wise parity-checked against
+    the FP64 oracle).  Bars: FP32 1e-5, FP16 1e-3 (the stated bars); BF16
+    misses 1e-3 by its format (see the 64^3 test) and is held to 1e-1."""
+    import torch
+    from paper_2609_09160_amd import Solver
+    n, steps = 512, 1000
+    m0 = inputs.solenoidal_field((n, n, n), device="cuda")
+
+    def u_after(storage):
+        s = Solver((n, n, n), 0.6, lattice=Q, storage=storage)
+        s.set_moments(m0)
+        s.step(steps)
+        out = torch.empty((10, n, n, n), dtype=torch.float32, device="cuda")
+        s.moments(out=out)
+        s.close()
+        u = out[1:4].double()
+        del out
+        torch.cuda.empty_cache()
+        return u
+
+    s = Solver((n, n, n), 0.6, lattice=Q, storage="f64")
+    s.set_moments(m0)
+    s.step(steps)
+    ref = s.moments()[1:4].clone()
+    s.close()
+    torch.cuda.empty_cache()
+    ref_norm = float(torch.linalg.vector_norm(ref))
+    bars = {"f32": 1e-5, "f16s": 1e-3, "bf16s": 1e-1}
+    for storage, bar in bars.items():
+        u = u_after(storage)
+        e = float(torch.linalg.vector_norm(u - ref)) / ref_norm
+        del u
+        torch.cuda.empty_cache()
+        say(f"512^3 Q{Q} {storage}: u rel L2 vs FP64 after {steps} steps = {e:.3e}")
+        assert e <= bar
+    del ref, m0
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("Q", [19, 27, "27h"])
@@ -123,8 +169,10 @@ def _golden(name):
 @pytest.mark.parametrize("Q", [19, 27, "27h"])
 def test_taylor_green_512(Q):
     """The paper's Taylor-Green validation at its own size: 512^3, nu = 0.04074,
-    U0 = 0.04, FP32.  A linear fit of log(E/E0) over the first 4000 steps gives
-    the effective viscosity, compared with the input and the printed fits."""
+    U0 = 0.04, FP32, 2000 steps.  Linear fits of log(E/E0) over the windows
+    [0, T], T = 250 ... 2000, give effective viscosities; the one over [0, 500]
+    (the initial decay) is held to 5e-3 of the input, and all are printed
+    beside the paper's fits."""
     import torch
     from paper_2609_09160_amd import Solver
     gd = _golden("taylor_green_512.txt")
