@@ -17,6 +17,7 @@ D3Q27, all host cores and one).
   python bench.py [--steps K] [--warmup W] [--lattice 19|27|27h]
                   [--storage f32|f64|f16s|bf16s] [--n 512] [--no-variants]
                   [--no-adjoint] [--no-accuracy] [--no-cpu-baseline] [--copy-probe]
+                  [--copy-ceilings]
 """
 import argparse
 import hashlib
@@ -134,14 +135,15 @@ def energy_run(n, lattice, storage, seconds=2.0):
             "steps": steps, "source": "amd-smi energy counter over the timed steps"}
 
 
-def run_gpu(n, lattice, storage, steps, warmup, m0=None, launch=(0, 0), energy=None):
+def run_gpu(n, lattice, storage, steps, warmup, m0=None, launch=(0, 0), energy=None,
+            rounding="nearest"):
     import torch
     from paper_2609_09160_amd import Solver
     shape = (n, n, n)
     own = m0 is None
     if own:
         m0 = make_input(shape, "cuda")
-    s = Solver(shape, 0.6, lattice=lattice, storage=storage)
+    s = Solver(shape, 0.6, lattice=lattice, storage=storage, rounding=rounding)
     if launch != (0, 0):
         s.set_launch(*launch)
     s.set_moments(m0)
@@ -224,6 +226,48 @@ def copy_ceiling(n=512 ** 3, nplanes=10, reps=5):
     del a, b
     torch.cuda.empty_cache()
     return 2 * 4 * nplanes * n / (best * 1e-3) / 1e9
+
+
+def copy_ceilings(n=512 ** 3, nplanes=10, reps=10):
+    """Copies of the step's volume (nplanes x n floats read, as many written)
+    by three independent routes, best of `reps` each, GB/s counting read +
+    write: the library's copy probe (16-byte accesses, non-temporal stores),
+    torch's copy_ between contiguous tensors (the HIP runtime's device-to-
+    device memcpy), and a torch elementwise kernel (b = a * 1)."""
+    import ctypes
+    import torch
+    from paper_2609_09160_amd import _lib
+    lib = _lib.load()
+    a = torch.rand(nplanes * n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
+    nbytes = 2 * 4 * nplanes * n
+
+    def best(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = None
+        for _ in range(reps):
+            st, en = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            st.record(stream)
+            fn()
+            en.record(stream)
+            torch.cuda.synchronize()
+            ms = st.elapsed_time(en)
+            t = ms if t is None else min(t, ms)
+        return round(nbytes / (t * 1e-3) / 1e9, 1)
+
+    probe = lambda: _lib.check(lib.lbfast_copy_probe(  # noqa: E731
+        ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), nplanes * n // 4,
+        ctypes.c_void_p(stream.cuda_stream)))
+    out = {"bytes_read": nbytes // 2, "bytes_written": nbytes // 2,
+           "library_copy_probe_GBs": best(probe),
+           "torch_copy_GBs": best(lambda: b.copy_(a)),
+           "torch_elementwise_GBs": best(lambda: torch.mul(a, 1.0, out=b))}
+    assert torch.equal(a[-4096:], b[-4096:])
+    del a, b
+    torch.cuda.empty_cache()
+    return out
 
 
 ADJ_BYTES_PER_LUP = 140   # adjoint step: read lambda' 40, F 12, u(t+1) 12, u(t) 12, gF 12;
@@ -353,9 +397,9 @@ ACCURACY_BARS = {"f32": 1e-5, "f16s": 1e-3, "bf16s": 1e-3}  # u rel L2 after 100
 
 def accuracy_vs_fp64(n, lattices, forms, steps=1000):
     """Relative L2 error of u after `steps` of the n^3 solenoidal workload for
-    each (lattice, storage) of `forms`, against the same run in FP64 on the GPU
-    (the FP64 path is element-wise parity-checked against the FP64 CPU
-    oracle)."""
+    each (lattice, storage, rounding) of `forms`, against the same run in FP64
+    on the GPU (the FP64 path is element-wise parity-checked against the FP64
+    CPU oracle)."""
     import torch
     from paper_2609_09160_amd import Solver
     m0 = make_input((n, n, n), "cuda")
@@ -369,8 +413,8 @@ def accuracy_vs_fp64(n, lattices, forms, steps=1000):
         del s
         torch.cuda.empty_cache()
         rn = float(torch.linalg.vector_norm(ref))
-        for st in [st for la, st in forms if la == lat]:
-            s = Solver((n, n, n), 0.6, lattice=lat, storage=st)
+        for st, rd in [(st, rd) for la, st, rd in forms if la == lat]:
+            s = Solver((n, n, n), 0.6, lattice=lat, storage=st, rounding=rd)
             s.set_moments(m0)
             s.step(steps)
             buf = torch.empty((10, n, n, n), dtype=torch.float32, device="cuda")
@@ -380,7 +424,7 @@ def accuracy_vs_fp64(n, lattices, forms, steps=1000):
             e = float(torch.linalg.vector_norm(buf[1:4].double() - ref)) / rn
             del buf
             torch.cuda.empty_cache()
-            out[(lat, st)] = e
+            out[(lat, st, rd)] = e
         del ref
         torch.cuda.empty_cache()
     del m0
@@ -450,6 +494,8 @@ def main():
     ap.add_argument("--z-chunk", type=int, default=0, help="launch override (0 = default)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the library's stream copy (counter calibration)")
+    ap.add_argument("--copy-ceilings", action="store_true",
+                    help="only time copies of the step's volume by three routes")
     args = ap.parse_args()
     args.lattice = args.lattice if args.lattice == "27h" else int(args.lattice)
 
@@ -464,6 +510,10 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+
+    if args.copy_ceilings:
+        print(json.dumps(copy_ceilings()), flush=True)
+        return
 
     if args.copy_probe:
         gbs, ms, nbytes = stream_ceiling()
@@ -517,36 +567,41 @@ def main():
     cgbs = copy_ceiling()
     out["roofline"]["measured_copy_GBs"] = round(cgbs, 1)
     out["roofline"]["frac_of_measured_copy"] = round(achieved / cgbs, 4)
+    VARIANTS = ((27, "f32", "nearest"), (19, "f16s", "nearest"), (19, "f16s", "stochastic"),
+                (19, "bf16s", "nearest"), (27, "f16s", "nearest"), (19, "f64", "nearest"),
+                ("27h", "f32", "nearest"), ("27h", "f16s", "nearest"), ("27h", "f64", "nearest"))
+
+    def vkey(lat, st, rd):
+        return f"d3q{lat}_{st}" + ("_stochastic" if rd == "stochastic" else "")
+
+    main_form = (args.lattice, args.storage, "nearest")
+    var = {}
     if not args.no_variants:
-        var = {}
-        for lat, st in ((27, "f32"), (19, "f16s"), (19, "bf16s"), (27, "f16s"), (19, "f64"),
-                        ("27h", "f32"), ("27h", "f16s"), ("27h", "f64")):
-            if (lat, st) == (args.lattice, args.storage):
+        for lat, st, rd in VARIANTS:
+            if (lat, st, rd) == main_form:
                 continue
-            r = run_gpu(n, lat, st, max(20, args.steps // 4), 5)
-            var[f"d3q{lat}_{st}"] = {"mlups": round(r["mlups"], 1),
-                                     "ms_per_step": round(r["ms_per_step"], 5),
-                                     "algorithmic_GBs": round(r["algorithmic_GBs"], 1),
-                                     "hbm_frac": round(r["hbm_frac"], 4)}
+            r = run_gpu(n, lat, st, max(20, args.steps // 4), 5, rounding=rd)
+            var[vkey(lat, st, rd)] = {"mlups": round(r["mlups"], 1),
+                                      "ms_per_step": round(r["ms_per_step"], 5),
+                                      "algorithmic_GBs": round(r["algorithmic_GBs"], 1),
+                                      "hbm_frac": round(r["hbm_frac"], 4)}
         out["variants"] = var
     if not args.no_accuracy and args.storage != "f64":
         # every benchmarked form that is not FP64 itself, at the benchmark's size
-        forms = [(args.lattice, args.storage)]
+        forms = [main_form]
         if not args.no_variants:
-            forms += [(lat, st) for lat, st in ((27, "f32"), (19, "f16s"), (19, "bf16s"),
-                                               (27, "f16s"), ("27h", "f32"), ("27h", "f16s"))
-                      if (lat, st) != (args.lattice, args.storage)]
-        lats = list(dict.fromkeys(lat for lat, _ in forms))
+            forms += [f for f in VARIANTS if f[1] != "f64" and f != main_form]
+        lats = list(dict.fromkeys(lat for lat, _, _ in forms))
         errs = accuracy_vs_fp64(n, lats, forms)
-        for (lat, st), e in errs.items():
+        for (lat, st, rd), e in errs.items():
             entry = {"u_rel_l2_vs_fp64": float(f"{e:.3g}"), "steps": 1000,
                      "bar": ACCURACY_BARS[st], "meets_bar": bool(e <= ACCURACY_BARS[st])}
-            if (lat, st) == (args.lattice, args.storage):
+            if (lat, st, rd) == main_form:
                 entry["reference"] = ("the same run in FP64 on the GPU (element-wise "
                                       "parity-checked against the FP64 CPU oracle)")
                 out["accuracy"] = entry
             else:
-                var[f"d3q{lat}_{st}"]["accuracy"] = entry
+                var[vkey(lat, st, rd)]["accuracy"] = entry
     if not args.no_adjoint:
         out["adjoint"] = run_adjoint()
     if not args.no_variants:

@@ -77,7 +77,9 @@ enum { LBF_D3Q19 = 19, LBF_D3Q27 = 27, LBF_D3Q27H = 270 };
  * F16S/BF16S = 16-bit storage of v/s_m with a power-of-two scale s_m per
  * moment plane, arithmetic in FP32 (only valid as `storage`).  In 16-bit
  * storage the second-order planes hold the deviation a2 - u u (u as stored),
- * p* and u are deviations already; the ABI always exchanges the total a2. */
+ * p* and u are deviations already; the ABI always exchanges the total a2.
+ * lbfast_set_moments rounds to nearest even; the step rounds as
+ * lbfast_params.rounding says. */
 enum { LBF_F64 = 0, LBF_F32 = 1, LBF_F16S = 2, LBF_BF16S = 3 };
 
 /* boundary per axis: periodic, or stationary halfway bounce-back walls at
@@ -96,8 +98,13 @@ typedef struct lbfast_params {
                            ignored while a force field is set */
   float scale[10];      /* 16-bit storage only: power-of-two scale per moment
                            plane; 0 = choose at the first set_moments as the
-                           power of two that maps max|v| (v the plane's total
-                           value) just below 2^10.  The scales then stay fixed:
+                           power of two that maps M just below 2^10, with M
+                           max|u| over the three velocity planes for each of
+                           them, max(|a2|, max|u|^2) over the six second-order
+                           planes for each of them, and max(|p*|, 3 max|u|^2)
+                           for p* (so that a plane that starts at zero, like
+                           p* of a solenoidal field, still gets a scale of its
+                           group's magnitude).  The scales then stay fixed:
                            FP16 storage overflows once a plane grows beyond
                            64 times its magnitude at that set_moments (a
                            channel driven from noise or from rest, a flow
@@ -105,8 +112,21 @@ typedef struct lbfast_params {
                            as LBF_E_NONFINITE; pass scales sized for the
                            largest expected values in such runs, and for a
                            state at rest, which has no magnitude to go by */
-  int32_t reserved[8];  /* must be zero */
+  int32_t rounding;     /* 16-bit storage only: how the step rounds p* and u,
+                           LBF_ROUND_NEAREST (0, to nearest even) or
+                           LBF_ROUND_STOCHASTIC (1: uniform bits from a hash
+                           of the site index and a seed drawn from the step
+                           count since create, so that changes below half a
+                           unit in the last place survive on average instead
+                           of being dropped at every step: slowly evolving
+                           flows do not stall, at the price of rounding noise);
+                           a2 - u u always rounds to nearest.  Runs are
+                           reproducible bit for bit from the same create; a
+                           restart into a new handle draws other bits */
+  int32_t reserved[7];  /* must be zero */
 } lbfast_params;
+
+enum { LBF_ROUND_NEAREST = 0, LBF_ROUND_STOCHASTIC = 1 };
 
 /* ABI version of the loaded library (LBFAST_ABI_VERSION at build time). */
 int lbfast_abi_version(void);
@@ -197,9 +217,11 @@ int lbfast_get_scales(lbfast_t h, float out[10]);
  * reproducible from run to run. */
 int lbfast_set_launch(lbfast_t h, int tile_rows, int z_chunk);
 
-/* Consecutive x-sites per lane: 1 (64-wide tiles) or 2 (128-wide tiles, one
+/* Consecutive x-sites per lane: 1 (64-wide tiles), 2 (128-wide tiles, one
  * 2-wide load or store per moment plane; needs an even nx and tiles of at
- * most 8 rows).  The default is 2 where nx is even and at least 128 and the
+ * most 8 rows) or 3 (192-wide tiles, 3-wide accesses; F32 storage, LBF_D3Q19
+ * or LBF_D3Q27, one component, nx divisible by 3, tiles of at most 8 rows;
+ * enabling the two-component variant returns to one site per lane).  The default is 2 where nx is even and at least 128 and the
  * 128-wide tiles leave no more of the last tile empty than 64-wide ones (1
  * for LBF_D3Q27H with F64 storage, where two sites spill registers).  If the
  * current tile height does not fit the 160 KiB of LDS with the new setting,

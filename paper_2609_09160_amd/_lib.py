@@ -18,6 +18,8 @@ LBF_E_DEVICE, LBF_E_NONFINITE, LBF_E_STATE = -4, -5, -6
 LBF_D3Q19, LBF_D3Q27, LBF_D3Q27H = 19, 27, 270
 LBF_F64, LBF_F32, LBF_F16S, LBF_BF16S = 0, 1, 2, 3
 LBF_PERIODIC, LBF_WALLS = 0, 1
+LBF_ROUND_NEAREST, LBF_ROUND_STOCHASTIC = 0, 1
+ROUNDING = {"nearest": LBF_ROUND_NEAREST, "stochastic": LBF_ROUND_STOCHASTIC}
 
 STORAGE = {"f64": LBF_F64, "f32": LBF_F32, "f16s": LBF_F16S, "bf16s": LBF_BF16S}
 LATTICE = {19: LBF_D3Q19, 27: LBF_D3Q27, "19": LBF_D3Q19, "27": LBF_D3Q27, "27h": LBF_D3Q27H,
@@ -31,7 +33,8 @@ class LbfastParams(ctypes.Structure):
                 ("storage", ctypes.c_int32), ("bc", ctypes.c_int32 * 3),
                 ("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
                 ("tau", ctypes.c_double), ("force", ctypes.c_double * 3),
-                ("scale", ctypes.c_float * 10), ("reserved", ctypes.c_int32 * 8)]
+                ("scale", ctypes.c_float * 10), ("rounding", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
 
 
 class LbfastPhaseParams(ctypes.Structure):
@@ -112,7 +115,7 @@ def declared_functions():
 
 
 def make_params(shape, tau, lattice=19, storage="f32", bc=(0, 0, 0), force=(0.0, 0.0, 0.0),
-                scale=None):
+                scale=None, rounding="nearest"):
     p = LbfastParams()
     p.struct_size = ctypes.sizeof(LbfastParams)
     p.lattice = LATTICE.get(lattice, lattice if isinstance(lattice, int) else -1)
@@ -124,4 +127,5 @@ def make_params(shape, tau, lattice=19, storage="f32", bc=(0, 0, 0), force=(0.0,
     p.tau = float(tau)
     for k in range(10):
         p.scale[k] = 0.0 if scale is None else float(scale[k])
+    p.rounding = ROUNDING[rounding] if isinstance(rounding, str) else int(rounding)
     return p

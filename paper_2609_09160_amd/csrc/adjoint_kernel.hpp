@@ -40,6 +40,7 @@ namespace lbf {
 template <int Q_, typename C_, bool FFIELD>
 struct Adjoint {
   static constexpr int Q = Q_;
+  static constexpr bool kThreeSites = false;
   using C = C_;
   using T = C_;
   // lambda(t+1) and F of a site; destinations also read u(t+1), u(t) and

@@ -32,6 +32,8 @@ struct StepArgs {
   double F[3];         // uniform force (used when Ffield == nullptr)
   float scale[10];     // 16-bit storage: value = scale * q
   float inv_scale[10];
+  uint32_t sr_seed;    // 16-bit storage: seed of this step's stochastic rounding
+  int stochastic;      // 16-bit storage: round p* and u stochastically
   // adjoint step only (src/dst then hold the adjoint variables at t+1 / t)
   const void* state_old;  // moments at t (10 planes; the velocity planes are read)
   const void* state_new;  // moments at t+1

@@ -109,7 +109,14 @@ constexpr int kD3Q27H = 270;
 // hardware range check against the plane size turns any out-of-range offset
 // into a zero load / dropped store instead of a fault.
 constexpr int kBufWord3 = 0x00020000;  // gfx9 family: 32-bit data format, raw access
-constexpr int kNonTemporal = 2;        // cache policy bit: nt
+#ifndef LBF_STORE_CPOL
+#define LBF_STORE_CPOL 2
+#endif
+constexpr int kNonTemporal = LBF_STORE_CPOL;  // cache policy of the plane stores (2: nt)
+#ifndef LBF_LOAD_CPOL
+#define LBF_LOAD_CPOL 0
+#endif
+constexpr int kLoadCpol = LBF_LOAD_CPOL;  // cache policy of the plane loads (0: default)
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), static_cast<short>(0),
@@ -119,12 +126,12 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, u
 template <typename V>
 __device__ __forceinline__ V buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   if constexpr (sizeof(V) == 2) {
-    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, kLoadCpol));
   } else if constexpr (sizeof(V) == 4) {
-    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kLoadCpol));
   } else {
     static_assert(sizeof(V) == 8, "2, 4 or 8 bytes");
-    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kLoadCpol));
   }
 }
 
@@ -143,7 +150,8 @@ __device__ __forceinline__ void buf_store_nt(V v, __amdgpu_buffer_rsrc_t r, uint
   }
 }
 
-// S consecutive values (S = 1 or 2) at byte offset off, one load instruction.
+// S consecutive values (S = 1, 2, or 3 for 4-byte elements) at byte offset
+// off, one load instruction.
 // The builtin's result is bit-cast as a whole to a vector of the element type
 // before its elements are taken: taking elements of the builtin's own
 // integer-vector result directly was compiled (ROCm 7.2) into a load of the
@@ -152,17 +160,24 @@ template <typename V, int S>
 __device__ __forceinline__ void buf_load_n(__amdgpu_buffer_rsrc_t r, uint32_t off, V (&out)[S]) {
   if constexpr (S == 1) {
     out[0] = buf_load<V>(r, off);
+  } else if constexpr (S == 3) {
+    static_assert(sizeof(V) == 4, "three values per lane: 4-byte elements");
+    using V3 = V __attribute__((ext_vector_type(3)));
+    const V3 w = __builtin_bit_cast(V3, __builtin_amdgcn_raw_buffer_load_b96(r, off, 0, kLoadCpol));
+    out[0] = w.x;
+    out[1] = w.y;
+    out[2] = w.z;
   } else {
-    static_assert(S == 2, "1 or 2 values per lane");
+    static_assert(S == 2, "1, 2 or 3 values per lane");
     using V2 = V __attribute__((ext_vector_type(2)));
     V2 w;
     if constexpr (sizeof(V) == 2) {
-      w = __builtin_bit_cast(V2, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+      w = __builtin_bit_cast(V2, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kLoadCpol));
     } else if constexpr (sizeof(V) == 4) {
-      w = __builtin_bit_cast(V2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+      w = __builtin_bit_cast(V2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kLoadCpol));
     } else {
       static_assert(sizeof(V) == 8, "2, 4 or 8 bytes");
-      w = __builtin_bit_cast(V2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+      w = __builtin_bit_cast(V2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kLoadCpol));
     }
     out[0] = w.x;
     out[1] = w.y;
@@ -175,8 +190,14 @@ __device__ __forceinline__ void buf_store_nt_n(const V (&v)[S], __amdgpu_buffer_
                                                uint32_t off) {
   if constexpr (S == 1) {
     buf_store_nt<V>(v[0], r, off);
+  } else if constexpr (S == 3) {
+    static_assert(sizeof(V) == 4, "three values per lane: 4-byte elements");
+    using U3 = unsigned int __attribute__((ext_vector_type(3)));
+    const U3 w = {__builtin_bit_cast(unsigned, v[0]), __builtin_bit_cast(unsigned, v[1]),
+                  __builtin_bit_cast(unsigned, v[2])};
+    __builtin_amdgcn_raw_buffer_store_b96(w, r, off, 0, kNonTemporal);
   } else {
-    static_assert(S == 2, "1 or 2 values per lane");
+    static_assert(S == 2, "1, 2 or 3 values per lane");
     using V2 = V __attribute__((ext_vector_type(2)));
     const V2 w = {v[0], v[1]};
     if constexpr (sizeof(V) == 2) {
@@ -252,6 +273,32 @@ __device__ __forceinline__ float bf16_bits_to_f32(uint16_t q) {
   return __uint_as_float(static_cast<uint32_t>(q) << 16);
 }
 
+// 32-bit integer hash "lowbias32" (C. Wellons, "Prospecting for hash
+// functions", 2018): xor-shift / multiply rounds with his published
+// constants; a counter-based source of uniform bits for stochastic rounding.
+__device__ __forceinline__ uint32_t hash32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352dU;
+  x ^= x >> 15;
+  x *= 0x846ca68bU;
+  x ^= x >> 16;
+  return x;
+}
+
+// Stochastic rounding of binary32 x to a format that keeps its top 32 - DROP
+// bits: r (8 uniform bits) is added at the top of the dropped bits and the
+// result truncated toward zero, so x rounds away from zero with probability
+// (dropped part) / 2^DROP, up to 2^-8 of a unit in the last kept place: an
+// unbiased rounding, which lets increments smaller than half a unit in the
+// last place accumulate instead of being rounded away at every step.
+template <int DROP>
+__device__ __forceinline__ float round_stochastic(float x, uint32_t r) {
+  uint32_t b = __float_as_uint(x);
+  b += r << (DROP - 8);
+  b &= ~((1u << DROP) - 1u);
+  return __uint_as_float(b);
+}
+
 template <>
 struct Storage<kF16S> {
   using T = uint16_t;
@@ -260,8 +307,18 @@ struct Storage<kF16S> {
   static __device__ __forceinline__ C load(const T* p, int64_t i, float s) {
     return f16_bits_to_f32(p[i]) * s;
   }
-  static __device__ __forceinline__ C decode(T q, float s) { return f16_bits_to_f32(q) * s; }
+  // q s as one mixed-precision multiply-add (the binary16 operand converted on
+  // the fly; exact, s being a power of two; +0 for a zero product)
+  static __device__ __forceinline__ C decode(T q, float s) {
+    return __builtin_fmaf(f16_bits_to_f32(q), s, 0.0f);
+  }
   static __device__ __forceinline__ T encode(C v, float inv_s) { return f32_to_f16_bits(v * inv_s); }
+  // stochastic rounding to binary16 (10 stored significand bits: 13 of
+  // binary32's are dropped; the truncated value converts exactly in the normal
+  // range, below it the conversion rounds to nearest)
+  static __device__ __forceinline__ T encode_sr(C v, float inv_s, uint32_t r) {
+    return f32_to_f16_bits(round_stochastic<13>(v * inv_s, r));
+  }
   static __device__ __forceinline__ void store(T* p, int64_t i, C v, float inv_s) {
     __builtin_nontemporal_store(f32_to_f16_bits(v * inv_s), p + i);
   }
@@ -280,6 +337,10 @@ struct Storage<kBF16S> {
   }
   static __device__ __forceinline__ C decode(T q, float s) { return bf16_bits_to_f32(q) * s; }
   static __device__ __forceinline__ T encode(C v, float inv_s) { return f32_to_bf16_bits(v * inv_s); }
+  // stochastic rounding to bfloat16 (the upper half of binary32)
+  static __device__ __forceinline__ T encode_sr(C v, float inv_s, uint32_t r) {
+    return static_cast<T>(__float_as_uint(round_stochastic<16>(v * inv_s, r)) >> 16);
+  }
   static __device__ __forceinline__ void store(T* p, int64_t i, C v, float inv_s) {
     __builtin_nontemporal_store(f32_to_bf16_bits(v * inv_s), p + i);
   }

@@ -106,8 +106,12 @@ int validate(const lbfast_params* p) {
     if (!is_pow2_float(p->scale[k]))
       return fail(LBF_E_ARG, "scale[%d] = %g is not a positive power of two", k, p->scale[k]);
   }
-  for (int k = 0; k < 8; ++k)
+  for (int k = 0; k < 7; ++k)
     if (p->reserved[k] != 0) return fail(LBF_E_ARG, "reserved[%d] must be zero", k);
+  if (p->rounding != LBF_ROUND_NEAREST && p->rounding != LBF_ROUND_STOCHASTIC)
+    return fail(LBF_E_ARG, "rounding must be LBF_ROUND_NEAREST or LBF_ROUND_STOCHASTIC");
+  if (p->rounding == LBF_ROUND_STOCHASTIC && !s16)
+    return fail(LBF_E_ARG, "stochastic rounding applies to 16-bit storage only");
   return LBF_OK;
 }
 
@@ -135,6 +139,7 @@ struct lbfast_ctx {
   double* d_partials = nullptr;  // kReduceBlocks*5 + 5 doubles
   unsigned* d_maxbits = nullptr; // 10
   int64_t N = 0;
+  uint64_t steps_done = 0;       // steps since create: seeds the stochastic rounding
 };
 
 namespace {
@@ -157,14 +162,26 @@ constexpr size_t kLdsLimit = 160 * 1024;
 // D3Q27h in FP64 keeps one site per lane (6 rows): two spill registers there.
 void default_launch(lbfast_ctx* h) {
   // two sites per lane unless 128-wide tiles would leave more of the last
-  // tile empty than 64-wide ones
-  const int64_t waste1 = ceil_div(h->p.nx, 64) * 64 - h->p.nx;
-  const int64_t waste2 = ceil_div(h->p.nx, 128) * 128 - h->p.nx;
-  h->lane_sites = (h->p.nx % 2 == 0 && h->p.nx >= 128 && waste2 <= waste1) ? 2 : 1;
+  // tile empty than 64-wide ones; else three (FP32, second-order sets) where
+  // 192-wide tiles leave no more empty than 64-wide ones (measured at 192^3:
+  // 143 us against 178 us per step with a force field, 6-row tiles)
+  const int64_t nx = h->p.nx;
+  const int64_t waste1 = ceil_div(nx, 64) * 64 - nx;
+  const int64_t waste2 = ceil_div(nx, 128) * 128 - nx;
+  const int64_t waste3 = ceil_div(nx, 192) * 192 - nx;
+  const bool three_ok = h->p.storage == LBF_F32 && h->p.lattice != LBF_D3Q27H && nx % 3 == 0 &&
+                        nx >= 192 && !h->two_phase;
+  if (nx % 2 == 0 && nx >= 128 && waste2 <= waste1)
+    h->lane_sites = 2;
+  else if (three_ok && waste3 <= waste1)
+    h->lane_sites = 3;
+  else
+    h->lane_sites = 1;
   if (h->p.lattice == LBF_D3Q27H && h->p.storage == LBF_F64) h->lane_sites = 1;
   h->tile_rows = 4;
   const bool f64 = h->p.storage == LBF_F64;
-  for (int ty : {f64 ? (h->lane_sites == 2 ? 4 : 6) : 8, 6, 4})
+  const int first = f64 ? (h->lane_sites == 2 ? 4 : 6) : (h->lane_sites == 3 ? 6 : 8);
+  for (int ty : {first, 6, 4})
     if (lds_bytes(h->p.lattice, h->p.storage, ty, h->lane_sites) <= kLdsLimit) {
       h->tile_rows = ty;
       break;
@@ -249,6 +266,7 @@ int step_args(const lbfast_ctx* h, lbf::StepArgs* a) {
     a->inv_scale[k] = h->inv_scale[k];
   }
   a->Ffield = h->Ffield;
+  a->stochastic = h->p.rounding == LBF_ROUND_STOCHASTIC;
   if (h->two_phase) {
     // the phases' relaxation times replace params.tau
     a->omega = 1.0 / h->pp.tau_l;
@@ -258,6 +276,16 @@ int step_args(const lbfast_ctx* h, lbf::StepArgs* a) {
     a->nu_h = (h->pp.tau_h - 0.5) / 3.0;
   }
   return LBF_OK;
+}
+
+// seed of the stochastic rounding of step t (16-bit storage): the step
+// counter through SplitMix64's output mix (Steele, Lea and Flood, 2014), so
+// that every step draws fresh bits per site
+uint32_t step_seed(uint64_t t) {
+  uint64_t x = t + 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return static_cast<uint32_t>(x ^ (x >> 31));
 }
 
 int launch_forward(const lbfast_ctx* h, const lbf::StepArgs& a) {
@@ -471,12 +499,16 @@ int lbfast_set_moments(lbfast_t h, const void* m, int dtype, int on_device) {
                          hipMemcpyHostToDevice, h->stream);
     return p;
   };
-  // automatic 16-bit scales: the power of two placing max|v| just below 2^10,
-  // which leaves a factor 64 of growth before FP16 overflows (65504); FP16
-  // keeps its relative precision down to 2^-14, far below any value that
-  // matters next to max|v|
-  // (v: the plane's total value, the deviation planes included)
+  // automatic 16-bit scales: the power of two placing the magnitude M of the
+  // plane's group just below 2^10, which leaves a factor 64 of growth before
+  // FP16 overflows (65504); FP16 keeps its relative precision down to 2^-14.
+  // M is max|u| for the velocity planes, max(|a2|, max|u|^2) for the
+  // second-order planes and max(|p*|, 3 max|u|^2) for p*: a plane that starts
+  // at zero (p* of a solenoidal field, u_z of a planar flow) takes its group's
+  // magnitude instead of a scale of 1, which would put its later values in
+  // FP16's subnormal range.
   if (!h->scales_fixed) {
+    float mx[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
       const int k0 = pass == 0 ? 0 : 4, k1 = pass == 0 ? 4 : 10;
       e = hipMemsetAsync(h->d_maxbits, 0, 16 * sizeof(unsigned), h->stream);
@@ -494,20 +526,29 @@ int lbfast_set_moments(lbfast_t h, const void* m, int dtype, int on_device) {
       if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
       if (e != hipSuccess) break;
       for (int k = k0; k < k1; ++k) {
+        std::memcpy(&mx[k], &bits[k], sizeof(float));
+        if (!std::isfinite(mx[k])) mx[k] = 0.0f;
+      }
+    }
+    if (e == hipSuccess) {
+      const float um = std::max(mx[1], std::max(mx[2], mx[3]));
+      float am = um * um;
+      for (int k = 4; k < 10; ++k) am = std::max(am, mx[k]);
+      const float pm = std::max(mx[0], 3.0f * um * um);
+      for (int k = 0; k < 10; ++k) {
         if (h->p.scale[k] != 0.0f) continue;
-        float mx;
-        std::memcpy(&mx, &bits[k], sizeof mx);
+        const float M = k == 0 ? pm : (k < 4 ? um : am);
         float sc = 1.0f;
-        if (mx > 0.0f && std::isfinite(mx)) {
+        if (M > 0.0f) {
           int ex;
-          std::frexp(mx, &ex);             // mx in [2^(ex-1), 2^ex)
-          sc = std::ldexp(1.0f, ex - 10);  // mx / sc < 2^10
+          std::frexp(M, &ex);              // M in [2^(ex-1), 2^ex)
+          sc = std::ldexp(1.0f, ex - 10);  // M / sc < 2^10
         }
         h->scale[k] = sc;
         h->inv_scale[k] = 1.0f / sc;
       }
+      h->scales_fixed = true;
     }
-    if (e == hipSuccess) h->scales_fixed = true;
   }
   void* dst = h->buf[h->cur];
   for (int k = 0; k < 10 && e == hipSuccess; ++k) {
@@ -587,8 +628,8 @@ int lbfast_set_launch(lbfast_t h, int tile_rows, int z_chunk) {
     bool ok = false;
     for (int t : lbf::kTileRowsSupported) ok = ok || t == tile_rows;
     if (!ok) return fail(LBF_E_ARG, "tile_rows %d not supported (4, 6, 8 or 14)", tile_rows);
-    if (h->lane_sites == 2 && tile_rows > 8)
-      return fail(LBF_E_UNSUPPORTED, "two x-sites per lane support tiles of at most 8 rows");
+    if (h->lane_sites >= 2 && tile_rows > 8)
+      return fail(LBF_E_UNSUPPORTED, "two or three x-sites per lane support tiles of at most 8 rows");
     if (h->p.lattice == LBF_D3Q27H && tile_rows > 8)
       return fail(LBF_E_UNSUPPORTED, "D3Q27h supports tiles of at most 8 rows");
     const size_t lb = lds_bytes(h->p.lattice, h->p.storage, tile_rows, h->lane_sites);
@@ -605,12 +646,17 @@ int lbfast_set_launch(lbfast_t h, int tile_rows, int z_chunk) {
 int lbfast_set_lane_sites(lbfast_t h, int sites) {
   g_err.clear();
   if (int rc = check_handle(h)) return rc;
-  if (sites != 1 && sites != 2) return fail(LBF_E_ARG, "sites must be 1 or 2");
+  if (sites != 1 && sites != 2 && sites != 3) return fail(LBF_E_ARG, "sites must be 1, 2 or 3");
   if (sites == 2 && h->p.nx % 2 != 0)
     return fail(LBF_E_UNSUPPORTED, "two x-sites per lane need an even nx");
+  if (sites == 3 && (h->p.nx % 3 != 0 || h->p.storage != LBF_F32 ||
+                     h->p.lattice == LBF_D3Q27H || h->two_phase))
+    return fail(LBF_E_UNSUPPORTED,
+                "three x-sites per lane need nx divisible by 3, F32 storage, a second-order "
+                "set and one component");
   // keep the tile height if it fits, else the tallest one (of 8, 6, 4) that does
   int ty = h->tile_rows;
-  if ((sites == 2 && ty > 8) || lds_bytes(h->p.lattice, h->p.storage, ty, sites) > kLdsLimit) {
+  if ((sites >= 2 && ty > 8) || lds_bytes(h->p.lattice, h->p.storage, ty, sites) > kLdsLimit) {
     ty = 0;
     for (int t : {8, 6, 4})
       if (lds_bytes(h->p.lattice, h->p.storage, t, sites) <= kLdsLimit) {
@@ -636,6 +682,7 @@ int lbfast_step(lbfast_t h, int64_t n) {
   for (int64_t s = 0; s < n; ++s) {
     a.src = h->buf[h->cur];
     a.dst = h->buf[h->cur ^ 1];
+    a.sr_seed = step_seed(h->steps_done++);
     if (h->two_phase) {
       // phi(t+1) and F(t+1) first: the correction needs the new force
       lbf::PhaseArgs pa = phase_args(h);
@@ -699,6 +746,15 @@ int lbfast_enable_two_phase(lbfast_t h, const lbfast_phase_params* pp) {
   h->pp = *pp;
   h->two_phase = true;
   h->pcur = 0;
+  if (h->lane_sites == 3) {
+    // the two-component step has one- and two-site forms only
+    h->lane_sites = 1;
+    for (int ty : {8, 6, 4})
+      if (lds_bytes(h->p.lattice, h->p.storage, ty, 1) <= kLdsLimit) {
+        h->tile_rows = ty;
+        break;
+      }
+  }
   // F(0) of phi = 0: the body force alone
   lbf::PhaseArgs pa = phase_args(h);
   pa.phi_out = h->phi[0];

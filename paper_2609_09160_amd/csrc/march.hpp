@@ -26,9 +26,9 @@
 //
 // gfx950 mapping (own design; the paper's 8x8x8 shared-memory tiles are prior
 // art for another GPU):
-//   * a workgroup owns a 64 S x TY column tile of the x-y plane (S = 1 or 2
-//     consecutive x-sites per lane, loaded and stored as one 1- or 2-wide
-//     access) and a chunk of z-planes, and marches through z;
+//   * a workgroup owns a 64 S x TY column tile of the x-y plane (S = 1, 2 or
+//     3 consecutive x-sites per lane, loaded and stored as one 1-, 2- or
+//     3-wide access) and a chunk of z-planes, and marches through z;
 //   * wave w (0..TY+1) handles tile row w-1; waves 0 and TY+1 are the y-halo
 //     rows and also compute the two x-halo columns (lanes 0..TY+1);
 //   * per source plane, every thread evaluates its own sites once and writes
@@ -158,8 +158,12 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
   // Hardware hands consecutive block ids to the 8 XCDs in turn; give each XCD
   // a contiguous range of logical tiles (y fastest, then x, then z chunk).
   const int nb = static_cast<int>(gridDim.x), b0 = static_cast<int>(blockIdx.x);
+#ifndef LBF_NO_XCD_REMAP
   const int q8 = nb >> 3, r8 = nb & 7, xcd = b0 & 7;
   int b = xcd * q8 + (xcd < r8 ? xcd : r8) + (b0 >> 3);
+#else
+  int b = b0 + 0 * nb;
+#endif
   const int tyi = b % a.tiles_y;
   b /= a.tiles_y;
   const int txi = b % a.tiles_x;
@@ -447,12 +451,18 @@ hipError_t launch_march_s(const StepArgs& a, hipStream_t stream) {
   }
 }
 
-// one or two consecutive x-sites per lane (a.lane_sites); the two-site form
-// exists for tiles of up to 8 rows (taller ones measured slower)
+// one, two or three consecutive x-sites per lane (a.lane_sites); the two-
+// and three-site forms exist for tiles of up to 8 rows (taller ones measured
+// slower), the three-site form (192-wide tiles) for 4-byte storage
 template <class P, int TY, bool WALLY>
 hipError_t launch_march(const StepArgs& a, hipStream_t stream) {
   if (a.lane_sites == 2) {
     if constexpr (TY <= 8) return launch_march_s<P, TY, WALLY, 2>(a, stream);
+    return hipErrorInvalidValue;
+  }
+  if (a.lane_sites == 3) {
+    if constexpr (TY <= 8 && sizeof(typename P::T) == 4 && P::kThreeSites)
+      return launch_march_s<P, TY, WALLY, 3>(a, stream);
     return hipErrorInvalidValue;
   }
   if (a.lane_sites != 1) return hipErrorInvalidValue;

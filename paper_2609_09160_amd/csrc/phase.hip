@@ -65,6 +65,18 @@ __device__ __forceinline__ C window_lap(const C (&n)[3][3], C own) {
   return sum141(r0, r1, r2);
 }
 
+// 1 / (sqrt(g2) + eps) for the interface normal: FP64 evaluates it exactly
+// rounded; FP32 uses the hardware square root and reciprocal (about one unit in
+// the last place each, against a sequence of some 16 instructions for the
+// correctly rounded pair)
+template <typename C>
+__device__ __forceinline__ C inv_norm_eps(C g2, C eps) {
+  if constexpr (std::is_same_v<C, float>)
+    return __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(g2) + eps);
+  else
+    return C(1) / (sqrt(g2) + eps);
+}
+
 // per-site record staged by the phase update: the total phase flux
 // V = phi u + lambda phi (1 - phi) grad(phi) / (|grad phi| + eps) (advection plus
 // interface compression, so that Eq. (2) reads phi' = phi - div(V) + D lap(phi))
@@ -232,8 +244,8 @@ __global__ void __launch_bounds__(64 * kUpdRows) phase_kernel(
           const C g[3] = {div_by<72>(gxm[k] + ds), div_by<72>(gym[k] + sd),
                           div_by<72>(gzm[k] + ss)};
           const C p = pv[k];
-          const C c =
-              lambda * p * (C(1) - p) / (sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + eps);
+          const C c = lambda * p * (C(1) - p) *
+                      inv_norm_eps(g[0] * g[0] + g[1] * g[1] + g[2] * g[2], eps);
           rv[k].vx = p * ux[b][i][k] + c * g[0];
           rv[k].vy = p * uy[b][i][k] + c * g[1];
           rv[k].vz = p * uz[b][i][k] + c * g[2];

@@ -31,20 +31,52 @@ namespace lbf {
 // Steps 1-2 at one source site: post-collision coefficients and the
 // reconstructed populations, kept in units of 1/D: g[i] = D f_i(y) with
 // D f_i = k_i [P0 - 1.5 tr P2 + 3 c.P1 + 4.5 c c : P2], k_i = D w_i.
-template <int Q, typename C, int SEL = kSelAll>
+// m[4..9] hold, by NEQ: kTotal, the total a2; kDev, a2 - u u (deviation
+// storage); kDevRelaxed, (1 - omega)(a2 - u u).
+// HASF = false: no force anywhere (uniform zero force, no field); the force
+// terms, identically zero, are left out.
+enum { kTotal = 0, kDev = 1, kDevRelaxed = 2 };
+template <int Q, typename C, int SEL = kSelAll, int NEQ = kTotal, bool HASF = true>
 __device__ __forceinline__ void source_pops(const C m[10], C Fx, C Fy, C Fz, C omega, C g[Q]) {
   const C h = C(0.5);
   const C om1 = C(1) - omega;
   const C ux = m[1], uy = m[2], uz = m[3];
-  const C P2xx = omega * ux * ux + om1 * m[4] + ux * Fx;
-  const C P2yy = omega * uy * uy + om1 * m[5] + uy * Fy;
-  const C P2zz = omega * uz * uz + om1 * m[6] + uz * Fz;
-  const C P2xy = omega * ux * uy + om1 * m[7] + h * (ux * Fy + uy * Fx);
-  const C P2xz = omega * ux * uz + om1 * m[8] + h * (ux * Fz + uz * Fx);
-  const C P2yz = omega * uy * uz + om1 * m[9] + h * (uy * Fz + uz * Fy);
+  // P2 = u u + (1 - omega)(a2 - u u) + (u F + F u)/2
+  C P2xx, P2yy, P2zz, P2xy, P2xz, P2yz;
+  if constexpr (NEQ == kDevRelaxed) {
+    P2xx = ux * ux + m[4];
+    P2yy = uy * uy + m[5];
+    P2zz = uz * uz + m[6];
+    P2xy = ux * uy + m[7];
+    P2xz = ux * uz + m[8];
+    P2yz = uy * uz + m[9];
+  } else if constexpr (NEQ == kDev) {
+    P2xx = ux * ux + om1 * m[4];
+    P2yy = uy * uy + om1 * m[5];
+    P2zz = uz * uz + om1 * m[6];
+    P2xy = ux * uy + om1 * m[7];
+    P2xz = ux * uz + om1 * m[8];
+    P2yz = uy * uz + om1 * m[9];
+  } else {
+    P2xx = omega * ux * ux + om1 * m[4];
+    P2yy = omega * uy * uy + om1 * m[5];
+    P2zz = omega * uz * uz + om1 * m[6];
+    P2xy = omega * ux * uy + om1 * m[7];
+    P2xz = omega * ux * uz + om1 * m[8];
+    P2yz = omega * uy * uz + om1 * m[9];
+  }
+  C Vx = C(3) * ux, Vy = C(3) * uy, Vz = C(3) * uz;
+  if constexpr (HASF) {
+    P2xx += ux * Fx;
+    P2yy += uy * Fy;
+    P2zz += uz * Fz;
+    P2xy += h * (ux * Fy + uy * Fx);
+    P2xz += h * (ux * Fz + uz * Fx);
+    P2yz += h * (uy * Fz + uz * Fy);
+    Vx = C(3) * (ux + h * Fx), Vy = C(3) * (uy + h * Fy), Vz = C(3) * (uz + h * Fz);
+  }
   // scaled coefficients of the reconstruction (cs^2 = 1/3)
   const C A = m[0] - C(1.5) * (P2xx + P2yy + P2zz);
-  const C Vx = C(3) * (ux + h * Fx), Vy = C(3) * (uy + h * Fy), Vz = C(3) * (uz + h * Fz);
   const C Dx = C(4.5) * P2xx, Dy = C(4.5) * P2yy, Dz = C(4.5) * P2zz;
   const C Oxy = C(9) * P2xy, Oxz = C(9) * P2xz, Oyz = C(9) * P2yz;
   expand<Q, C, SEL>(A, Dx, Dy, Dz, Oxy, Oxz, Oyz, Vx, Vy, Vz, g);
@@ -82,7 +114,7 @@ __device__ __forceinline__ void source_pops(const C m[10], C Fx, C Fy, C Fz, C o
 //   f(c_z = +-1) = Q1 / 2 + R +- (3/2 u_z Q2 + 3/2 gam + Bf / 2).
 // Every intermediate is a deviation of order u, B or F (the rest weights
 // cancel in P), so FP32 keeps its precision relative to the flow.
-template <typename C, int SEL = kSelAll>
+template <typename C, int SEL = kSelAll, int NEQ = kTotal, bool HASF = true>
 __device__ __forceinline__ void source_pops_full(const C m[10], C Fx, C Fy, C Fz, C omega,
                                                  C g[27]) {
   using L = Lat<27>;
@@ -90,13 +122,25 @@ __device__ __forceinline__ void source_pops_full(const C m[10], C Fx, C Fy, C Fz
   const C om1 = C(1) - omega;
   const C ux = m[1], uy = m[2], uz = m[3];
   // (1 - omega) a2neq
-  const C Bxx = om1 * (m[4] - ux * ux), Byy = om1 * (m[5] - uy * uy);
-  const C Bzz = om1 * (m[6] - uz * uz), Bxy = om1 * (m[7] - ux * uy);
-  const C Bxz = om1 * (m[8] - ux * uz), Byz = om1 * (m[9] - uy * uz);
-  // Hermite coefficient of the Guo term, (u F + F u) / 2
-  const C Mxx = ux * Fx, Myy = uy * Fy, Mzz = uz * Fz;
-  const C Mxy = h * (ux * Fy + uy * Fx), Mxz = h * (ux * Fz + uz * Fx);
-  const C Myz = h * (uy * Fz + uz * Fy);
+  C Bxx, Byy, Bzz, Bxy, Bxz, Byz;
+  if constexpr (NEQ == kDevRelaxed) {
+    Bxx = m[4], Byy = m[5], Bzz = m[6];
+    Bxy = m[7], Bxz = m[8], Byz = m[9];
+  } else if constexpr (NEQ == kDev) {
+    Bxx = om1 * m[4], Byy = om1 * m[5], Bzz = om1 * m[6];
+    Bxy = om1 * m[7], Bxz = om1 * m[8], Byz = om1 * m[9];
+  } else {
+    Bxx = om1 * (m[4] - ux * ux), Byy = om1 * (m[5] - uy * uy);
+    Bzz = om1 * (m[6] - uz * uz), Bxy = om1 * (m[7] - ux * uy);
+    Bxz = om1 * (m[8] - ux * uz), Byz = om1 * (m[9] - uy * uz);
+  }
+  // Hermite coefficient of the Guo term, (u F + F u) / 2 (zero without force)
+  C Mxx = C(0), Myy = C(0), Mzz = C(0), Mxy = C(0), Mxz = C(0), Myz = C(0);
+  if constexpr (HASF) {
+    Mxx = ux * Fx, Myy = uy * Fy, Mzz = uz * Fz;
+    Mxy = h * (ux * Fy + uy * Fx), Mxz = h * (ux * Fz + uz * Fx);
+    Myz = h * (uy * Fz + uz * Fy);
+  }
   constexpr C W[3] = {C(0.5), C(2), C(0.5)};
   constexpr C sv[3] = {C(1.5), C(-3), C(1.5)};
   // per-axis factors of x and y, and their products with the column terms
@@ -111,8 +155,11 @@ __device__ __forceinline__ void source_pops_full(const C m[10], C Fx, C Fy, C Fz
     for (int c = 0; c < 3; ++c) Ex[c] = W[c] + ex[c], Ey[c] = W[c] + ey[c];
   }
   // p* and the x, y parts of the force term: 3/2 c F_a + 9/2 M_aa (c^2 - 1/3)
-  const C fx[3] = {C(-1.5) * Fx + C(3) * Mxx, C(-1.5) * Mxx, C(1.5) * Fx + C(3) * Mxx};
-  const C fy[3] = {C(-1.5) * Fy + C(3) * Myy, C(-1.5) * Myy, C(1.5) * Fy + C(3) * Myy};
+  C fx[3] = {C(0), C(0), C(0)}, fy[3] = {C(0), C(0), C(0)};
+  if constexpr (HASF) {
+    fx[0] = C(-1.5) * Fx + C(3) * Mxx, fx[1] = C(-1.5) * Mxx, fx[2] = C(1.5) * Fx + C(3) * Mxx;
+    fy[0] = C(-1.5) * Fy + C(3) * Myy, fy[1] = C(-1.5) * Myy, fy[2] = C(1.5) * Fy + C(3) * Myy;
+  }
   const C h2 = C(1.5) * uz * uz, h1 = C(1.5) * uz;
   static_for<9>([&](auto J) {
     constexpr int cx = decltype(J)::value / 3, cy = decltype(J)::value % 3;
@@ -123,14 +170,18 @@ __device__ __forceinline__ void source_pops_full(const C m[10], C Fx, C Fy, C Fz
     const C P = ex[cx] * Ey[cy] + W[cx] * ey[cy];
     const C al = Bxx * sv[cx] * Ey[cy] + Byy * sv[cy] * Ex[cx] + Bxy * dx[cx] * dy[cy];
     const C gam = Bxz * dx[cx] * Ey[cy] + Byz * dy[cy] * Ex[cx];
-    const C bet = Bzz * Exy + WW * Mzz;
-    const C A = WW * (m[0] + fx[cx] + fy[cy] + sxy * Mxy);
-    const C Bf = WW * (C(1.5) * Fz + sx * Mxz + sy * Myz);
+    C bet = Bzz * Exy, A = WW * m[0], Bf = C(0);
+    if constexpr (HASF) {
+      bet += WW * Mzz;
+      A = WW * (m[0] + fx[cx] + fy[cy] + sxy * Mxy);
+      Bf = WW * (C(1.5) * Fz + sx * Mxz + sy * Myz);
+    }
     const C Q1 = P + al + A;
     const C Q2 = Exy + al;
     const C R = h2 * Q2 + C(1.5) * bet + C(2) * h1 * gam;
     const C even = h * Q1 + R;
-    const C odd = h1 * Q2 + C(1.5) * gam + h * Bf;
+    C odd = h1 * Q2 + C(1.5) * gam;
+    if constexpr (HASF) odd += h * Bf;
     g[L::index(cx - 1, cy - 1, 0)] = C(2) * (Q1 - R);
     g[L::index(cx - 1, cy - 1, 1)] = even + odd;
     g[L::index(cx - 1, cy - 1, -1)] = even - odd;
@@ -140,24 +191,31 @@ __device__ __forceinline__ void source_pops_full(const C m[10], C Fx, C Fy, C Fz
 // Steps 4-5 at one destination site: the running projections (units of 1/D)
 // become the moments of the new time level, with the force-consistent
 // correction.
-template <int Q, typename C>
+template <int Q, typename C, bool HASF = true>
 __device__ __forceinline__ void finalize(const Sums<C>& S, C Fx, C Fy, C Fz, C out[10]) {
   constexpr int D = Lat<Q>::D;
   const C h = C(0.5);
-  const C ux = div_by<D>(S.jx) + h * Fx;
-  const C uy = div_by<D>(S.jy) + h * Fy;
-  const C uz = div_by<D>(S.jz) + h * Fz;
+  C ux = div_by<D>(S.jx), uy = div_by<D>(S.jy), uz = div_by<D>(S.jz);
+  if constexpr (HASF) ux += h * Fx, uy += h * Fy, uz += h * Fz;
   out[0] = div_by<D>(S.s0);
   out[1] = ux;
   out[2] = uy;
   out[3] = uz;
   // H2 diagonal: sum c_a^2 f - cs^2 sum f = (3 sum c_a^2 f - sum f) / 3
-  out[4] = div_by<3 * D>(C(3) * S.pxx - S.s0) + Fx * ux;
-  out[5] = div_by<3 * D>(C(3) * S.pyy - S.s0) + Fy * uy;
-  out[6] = div_by<3 * D>(C(3) * S.pzz - S.s0) + Fz * uz;
-  out[7] = div_by<D>(S.pxy) + h * (Fx * uy + Fy * ux);
-  out[8] = div_by<D>(S.pxz) + h * (Fx * uz + Fz * ux);
-  out[9] = div_by<D>(S.pyz) + h * (Fy * uz + Fz * uy);
+  out[4] = div_by<3 * D>(C(3) * S.pxx - S.s0);
+  out[5] = div_by<3 * D>(C(3) * S.pyy - S.s0);
+  out[6] = div_by<3 * D>(C(3) * S.pzz - S.s0);
+  out[7] = div_by<D>(S.pxy);
+  out[8] = div_by<D>(S.pxz);
+  out[9] = div_by<D>(S.pyz);
+  if constexpr (HASF) {
+    out[4] += Fx * ux;
+    out[5] += Fy * uy;
+    out[6] += Fz * uz;
+    out[7] += h * (Fx * uy + Fy * ux);
+    out[8] += h * (Fx * uz + Fz * ux);
+    out[9] += h * (Fy * uz + Fz * uy);
+  }
 }
 
 // The forward step as a physics policy of the z-march: a site reads its 10
@@ -169,15 +227,22 @@ __device__ __forceinline__ void finalize(const Sums<C>& S, C Fx, C Fy, C Fz, C o
 // relaxes with omega(phi(t)) and applies F(t) / rho(phi(t)), the correction
 // applies F(t+1) / rho(phi(t+1)).
 // FULL: D3Q27h, the source populations over the complete Hermite basis.
-template <int Q_, int ST, bool FFIELD, bool FNEXT = false, bool VAR = false, bool FULL = false>
+// NOF: no force at all (a zero uniform force and no field): the Guo source and
+// the force terms of the correction vanish and are not evaluated.
+template <int Q_, int ST, bool FFIELD, bool FNEXT = false, bool VAR = false, bool FULL = false,
+          bool NOF = false>
 struct Forward {
   static_assert(FFIELD || !FNEXT, "a time-dependent force is a force field");
   static_assert(FNEXT || !VAR, "variable properties come with the two-component force");
   static_assert(!FULL || Q_ == 27, "the complete Hermite basis is the D3Q27 one");
+  static_assert(!NOF || !FFIELD, "no force means no force field");
   static constexpr int Q = Q_;
   using S = Storage<ST>;
   using C = typename S::C;
   using T = typename S::T;
+  // 192-wide tiles (three x-sites per lane) are built for the one-component
+  // second-order sets in FP32 storage
+  static constexpr bool kThreeSites = ST == kF32 && !FNEXT && !FULL;
   // raw (still encoded) moments and force of one site, fetched a plane ahead;
   // destinations of a time-dependent force also fetch F(t+1)
   template <bool OWN>
@@ -243,12 +308,18 @@ struct Forward {
   template <bool OWN, int SEL>
   static __device__ __forceinline__ void source(const StepArgs& a, const Raw<OWN>& r, C g[Q],
                                                 Carry& c) {
+    // Deviation storage keeps a2 - u u in m[4..9]: the source takes it as is,
+    // and with one relaxation rate for all sites already multiplied by
+    // (1 - omega) through the decode factor (1 - omega) s_k, exact as s_k is a
+    // power of two, so that q (1 - omega) s_k rounds like (1 - omega)(q s_k).
+    constexpr int kNeqMode = !S::kNeq ? kTotal : (VAR ? kDev : kDevRelaxed);
     C m[10];
 #pragma unroll
-    for (int k = 0; k < 10; ++k) m[k] = S::decode(r.m[k], a.scale[k]);
-    if constexpr (S::kNeq) {
-#pragma unroll
-      for (int k = 4; k < 10; ++k) m[k] += m[1 + a2_a(k)] * m[1 + a2_b(k)];
+    for (int k = 0; k < 10; ++k) {
+      float sk = a.scale[k];
+      if constexpr (kNeqMode == kDevRelaxed)
+        sk = k >= 4 ? (1.0f - static_cast<float>(a.omega)) * sk : sk;
+      m[k] = S::decode(r.m[k], sk);
     }
     C F[3];
 #pragma unroll
@@ -279,9 +350,9 @@ struct Forward {
       }
     }
     if constexpr (FULL)
-      source_pops_full<C, SEL>(m, F[0], F[1], F[2], omega, g);
+      source_pops_full<C, SEL, kNeqMode, !NOF>(m, F[0], F[1], F[2], omega, g);
     else
-      source_pops<Q, C, SEL>(m, F[0], F[1], F[2], omega, g);
+      source_pops<Q, C, SEL, kNeqMode, !NOF>(m, F[0], F[1], F[2], omega, g);
   }
 
   template <int NS>
@@ -290,24 +361,43 @@ struct Forward {
                                                 uint32_t plane_bytes) {
     T* __restrict__ dst = static_cast<T*>(a.dst);
     C out[NS][10];
+    T q[NS][10];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      finalize<Q, C>(acc[s], c[s].F[0], c[s].F[1], c[s].F[2], out[s]);
+      finalize<Q, C, !NOF>(acc[s], c[s].F[0], c[s].F[1], c[s].F[2], out[s]);
       if constexpr (S::kNeq) {
-        // store a2 - u u with the velocity as it will be read back
+        // 16-bit storage.  p* and u round to nearest, or stochastically (8
+        // bits each of one hash of the site index and this step's seed): the
+        // planes that accumulate over the steps, where rounding to nearest
+        // drops every change below half a unit in the last place and a slowly
+        // evolving flow stalls.  a2 - u u, relaxed at every step, rounds to
+        // nearest, with the velocity as it will be read back.
+        if (a.stochastic) {
+          const uint32_t site = static_cast<uint32_t>(pb) + off / sizeof(T) + s;
+          const uint32_t h = hash32(site ^ a.sr_seed);
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            q[s][k] = S::encode_sr(out[s][k], a.inv_scale[k], (h >> (8 * k)) & 0xffu);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) q[s][k] = S::encode(out[s][k], a.inv_scale[k]);
+        }
         C ur[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-          ur[k] = S::decode(S::encode(out[s][1 + k], a.inv_scale[1 + k]), a.scale[1 + k]);
+        for (int k = 0; k < 3; ++k) ur[k] = S::decode(q[s][1 + k], a.scale[1 + k]);
 #pragma unroll
-        for (int k = 4; k < 10; ++k) out[s][k] -= ur[a2_a(k)] * ur[a2_b(k)];
+        for (int k = 4; k < 10; ++k)
+          q[s][k] = S::encode(out[s][k] - ur[a2_a(k)] * ur[a2_b(k)], a.inv_scale[k]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 10; ++k) q[s][k] = S::encode(out[s][k], a.inv_scale[k]);
       }
     }
 #pragma unroll
     for (int k = 0; k < 10; ++k) {
       T v[NS];
 #pragma unroll
-      for (int s = 0; s < NS; ++s) v[s] = S::encode(out[s][k], a.inv_scale[k]);
+      for (int s = 0; s < NS; ++s) v[s] = q[s][k];
       buf_store_nt_n<T, NS>(v, plane_rsrc(dst + (k * a.N + pb), plane_bytes), off);
     }
   }
@@ -323,6 +413,10 @@ hipError_t launch_step_t(const StepArgs& a, hipStream_t stream) {
     if (a.Fnext) return launch_march<Forward<Q, ST, true, true, false, FULL>, TY, WALLY>(a, stream);
   }
   if (a.Fnext) return hipErrorInvalidValue;
+  if constexpr (!FFIELD) {
+    if (a.F[0] == 0.0 && a.F[1] == 0.0 && a.F[2] == 0.0)
+      return launch_march<Forward<Q, ST, false, false, false, FULL, true>, TY, WALLY>(a, stream);
+  }
   return launch_march<Forward<Q, ST, FFIELD, false, false, FULL>, TY, WALLY>(a, stream);
 }
 
@@ -340,6 +434,14 @@ hipError_t launch_step_t(const StepArgs& a, hipStream_t stream) {
 template <int ST>
 hipError_t launch_step_storage(int lattice, int tile_rows, bool walls_y, bool ffield,
                                const StepArgs& a, hipStream_t s) {
+#ifdef LBF_TUNE_ONLY
+  // tuning builds: D3Q19 with 6- and 8-row tiles only
+  if (lattice == 19) {
+    LBF_CASE(19, false, 6)
+    LBF_CASE(19, false, 8)
+  }
+  return hipErrorInvalidValue;
+#endif
   if (lattice == 19) {
     LBF_CASE(19, false, 4)
     LBF_CASE(19, false, 6)
@@ -357,6 +459,9 @@ hipError_t launch_step_storage(int lattice, int tile_rows, bool walls_y, bool ff
 template <int ST>
 hipError_t launch_step_storage_full(int tile_rows, bool walls_y, bool ffield, const StepArgs& a,
                                     hipStream_t s) {
+#ifdef LBF_TUNE_ONLY
+  return hipErrorInvalidValue;
+#endif
   LBF_CASE(27, true, 4)
   LBF_CASE(27, true, 6)
   LBF_CASE(27, true, 8)

@@ -16,13 +16,15 @@ class Solver:
 
     shape = (nx, ny, nz); lattice in {19, 27, "27h"} ("27h": the D3Q27 set
     with the complete Hermite basis); storage in {"f64", "f32", "f16s", "bf16s"};
-    bc = per-axis 0 (periodic) / 1 (walls, y only); force = uniform body force.
+    bc = per-axis 0 (periodic) / 1 (walls, y only); force = uniform body force;
+    rounding = "nearest" or "stochastic" (16-bit storage: how the step rounds
+    p* and u).
     The two flip/flop moment buffers are torch allocations on `device`, the
     launches go to torch's current stream of that device.
     """
 
     def __init__(self, shape, tau, lattice=19, storage="f32", bc=(0, 0, 0),
-                 force=(0.0, 0.0, 0.0), scale=None, device=None):
+                 force=(0.0, 0.0, 0.0), scale=None, device=None, rounding="nearest"):
         import torch
         self._torch = torch
         self.lib = _lib.load()
@@ -31,7 +33,8 @@ class Solver:
         self.storage = storage
         self.compute_dtype = torch.float64 if storage == "f64" else torch.float32
         self.device = torch.device(device if device is not None else "cuda")
-        self.params = _lib.make_params(self.shape, tau, lattice, storage, bc, force, scale)
+        self.params = _lib.make_params(self.shape, tau, lattice, storage, bc, force, scale,
+                                       rounding)
         nbytes = self.lib.lbfast_buffer_bytes(ctypes.byref(self.params))
         if nbytes == 0:
             check(_lib.LBF_E_ARG)

@@ -13,11 +13,12 @@ def say(*a):
 
 
 def gpu_run(shape, tau, m0, steps, lattice=19, storage="f64", bc=(0, 0, 0), force=(0, 0, 0),
-            Ffield=None, launch=None, scale=None):
+            Ffield=None, launch=None, scale=None, rounding="nearest"):
     """Run the HIP path; returns host float64 moments [10, nz, ny, nx]."""
     import torch
     from paper_2609_09160_amd import Solver
-    s = Solver(shape, tau, lattice=lattice, storage=storage, bc=bc, force=force, scale=scale)
+    s = Solver(shape, tau, lattice=lattice, storage=storage, bc=bc, force=force, scale=scale,
+               rounding=rounding)
     if launch:
         s.set_launch(*launch)
     s.set_moments(np.ascontiguousarray(m0))

@@ -71,6 +71,37 @@ def test_ragged_fp64(Q, shape, forcing, walls, sites):
     assert err <= 1e-12
 
 
+@pytest.mark.parametrize("Q", [19, 27])
+@pytest.mark.parametrize("shape", [(195, 13, 20), (192, 6, 3), (3, 5, 4)])
+@pytest.mark.parametrize("forcing", ["none", "uniform", "field"])
+@pytest.mark.parametrize("walls", [False, True])
+def test_three_sites_fp32(Q, shape, forcing, walls):
+    """Three x-sites per lane (192-wide tiles, FP32 storage only): a full tile
+    plus a ragged 3-site tail, one exact tile, and a grid narrower than one
+    lane's sites times a wave; off-equilibrium random state, no force, a
+    uniform or a per-site force, periodic or y-walls, 6 steps against the FP64
+    oracle: max error <= 1e-6 of each moment group (FP32 storage rounding)."""
+    tau = 0.7
+    bc = (0, 1 if walls else 0, 0)
+    m0 = inputs.random_state(shape, seed=sum(shape) + Q)
+    F = inputs.random_force(shape, seed=8, std=1e-4)
+    Fu = (2e-5, -1e-5, 3e-5)
+    say(f"three sites fp32 Q{Q} {shape} {forcing} walls={walls}")
+    kw = dict(lattice=Q, bc=bc, storage="f32", launch=(6, 0, 3))
+    if forcing == "none":
+        got = gpu_run(shape, tau, m0, 6, **kw)
+        want = oracle_run(shape, tau, m0, 6, lattice=Q, bc=bc)
+    elif forcing == "uniform":
+        got = gpu_run(shape, tau, m0, 6, force=Fu, **kw)
+        want = oracle_run(shape, tau, m0, 6, lattice=Q, bc=bc, force=np.array(Fu))
+    else:
+        got = gpu_run(shape, tau, m0, 6, Ffield=F.astype(np.float32), **kw)
+        want = oracle_run(shape, tau, m0, 6, lattice=Q, bc=bc, force=F.astype(np.float32).astype(np.float64))
+    err = group_rel_err(got, want)
+    say(f"  err {err:.3e}")
+    assert err <= 1e-6
+
+
 @pytest.mark.parametrize("Q", [19, 27, "27h"])
 def test_fp32_solenoidal_1000_steps(Q):
     """The 512^3 throughput workload's family at 64^3: random solenoidal field
