@@ -136,7 +136,7 @@ def energy_run(n, lattice, storage, seconds=2.0):
 
 
 def run_gpu(n, lattice, storage, steps, warmup, m0=None, launch=(0, 0), energy=None,
-            rounding="nearest"):
+            rounding="auto"):
     import torch
     from paper_2609_09160_amd import Solver
     shape = (n, n, n)
@@ -567,14 +567,15 @@ def main():
     cgbs = copy_ceiling()
     out["roofline"]["measured_copy_GBs"] = round(cgbs, 1)
     out["roofline"]["frac_of_measured_copy"] = round(achieved / cgbs, 4)
-    VARIANTS = ((27, "f32", "nearest"), (19, "f16s", "nearest"), (19, "f16s", "stochastic"),
-                (19, "bf16s", "nearest"), (27, "f16s", "nearest"), (19, "f64", "nearest"),
-                ("27h", "f32", "nearest"), ("27h", "f16s", "nearest"), ("27h", "f64", "nearest"))
+    # (lattice, storage, rounding of p* and u; "auto": FP16 to nearest, BF16 stochastic)
+    VARIANTS = ((27, "f32", "auto"), (19, "f16s", "auto"), (19, "f16s", "stochastic"),
+                (19, "bf16s", "auto"), (27, "f16s", "auto"), (19, "f64", "auto"),
+                ("27h", "f32", "auto"), ("27h", "f16s", "auto"), ("27h", "f64", "auto"))
 
     def vkey(lat, st, rd):
         return f"d3q{lat}_{st}" + ("_stochastic" if rd == "stochastic" else "")
 
-    main_form = (args.lattice, args.storage, "nearest")
+    main_form = (args.lattice, args.storage, "auto")
     var = {}
     if not args.no_variants:
         for lat, st, rd in VARIANTS:

@@ -113,8 +113,11 @@ typedef struct lbfast_params {
                            largest expected values in such runs, and for a
                            state at rest, which has no magnitude to go by */
   int32_t rounding;     /* 16-bit storage only: how the step rounds p* and u,
-                           LBF_ROUND_NEAREST (0, to nearest even) or
-                           LBF_ROUND_STOCHASTIC (1: uniform bits from a hash
+                           LBF_ROUND_AUTO (0: to nearest for F16S, stochastic
+                           for BF16S, whose 8-bit significand drops nearly
+                           every per-step change of a slowly evolving flow),
+                           LBF_ROUND_NEAREST (1, to nearest even) or
+                           LBF_ROUND_STOCHASTIC (2: uniform bits from a hash
                            of the site index and a seed drawn from the step
                            count since create, so that changes below half a
                            unit in the last place survive on average instead
@@ -126,7 +129,7 @@ typedef struct lbfast_params {
   int32_t reserved[7];  /* must be zero */
 } lbfast_params;
 
-enum { LBF_ROUND_NEAREST = 0, LBF_ROUND_STOCHASTIC = 1 };
+enum { LBF_ROUND_AUTO = 0, LBF_ROUND_NEAREST = 1, LBF_ROUND_STOCHASTIC = 2 };
 
 /* ABI version of the loaded library (LBFAST_ABI_VERSION at build time). */
 int lbfast_abi_version(void);
@@ -300,6 +303,12 @@ int lbfast_get_phase(lbfast_t h, void* phi, int dtype, int on_device);
  * Both calls are asynchronous on the handle's stream; the handle's own
  * state is left at m(T).  nsteps = 0 gives gF = 0 and lambda0 = lambda_T. */
 int lbfast_forward_checkpointed(lbfast_t h, int64_t nsteps, int64_t every, void* ckpt_dev);
+/* Launch shape of the adjoint step: x-sites per lane (0 = automatic, 1, or 2
+ * or 3 for F32 storage with nx divisible by it) and tile rows (0 = automatic,
+ * 4, 6, 8 or 14; with two or three sites per lane 4 or 6, and 4 for
+ * LBF_D3Q27).  Automatic: one site per lane, 8-row tiles (F64: 6).  Every
+ * shape computes the same formulas; results may differ in the last bits. */
+int lbfast_set_adjoint_launch(lbfast_t h, int sites, int tile_rows);
 size_t lbfast_adjoint_work_bytes(lbfast_t h, int64_t every);
 int lbfast_adjoint(lbfast_t h, int64_t nsteps, int64_t every, const void* ckpt_dev,
                    const void* lambda_T_dev, void* gF_dev, void* lambda0_dev, void* work_dev);

@@ -18,8 +18,9 @@ LBF_E_DEVICE, LBF_E_NONFINITE, LBF_E_STATE = -4, -5, -6
 LBF_D3Q19, LBF_D3Q27, LBF_D3Q27H = 19, 27, 270
 LBF_F64, LBF_F32, LBF_F16S, LBF_BF16S = 0, 1, 2, 3
 LBF_PERIODIC, LBF_WALLS = 0, 1
-LBF_ROUND_NEAREST, LBF_ROUND_STOCHASTIC = 0, 1
-ROUNDING = {"nearest": LBF_ROUND_NEAREST, "stochastic": LBF_ROUND_STOCHASTIC}
+LBF_ROUND_AUTO, LBF_ROUND_NEAREST, LBF_ROUND_STOCHASTIC = 0, 1, 2
+ROUNDING = {"auto": LBF_ROUND_AUTO, "nearest": LBF_ROUND_NEAREST,
+            "stochastic": LBF_ROUND_STOCHASTIC}
 
 STORAGE = {"f64": LBF_F64, "f32": LBF_F32, "f16s": LBF_F16S, "bf16s": LBF_BF16S}
 LATTICE = {19: LBF_D3Q19, 27: LBF_D3Q27, "19": LBF_D3Q19, "27": LBF_D3Q27, "27h": LBF_D3Q27H,
@@ -91,6 +92,7 @@ def load():
         "lbfast_forward_checkpointed": ([vp, i64, i64, vp], i32),
         "lbfast_adjoint_work_bytes": ([vp, i64], ctypes.c_size_t),
         "lbfast_adjoint": ([vp, i64, i64, vp, vp, vp, vp, vp], i32),
+        "lbfast_set_adjoint_launch": ([vp, i32, i32], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -115,7 +117,7 @@ def declared_functions():
 
 
 def make_params(shape, tau, lattice=19, storage="f32", bc=(0, 0, 0), force=(0.0, 0.0, 0.0),
-                scale=None, rounding="nearest"):
+                scale=None, rounding="auto"):
     p = LbfastParams()
     p.struct_size = ctypes.sizeof(LbfastParams)
     p.lattice = LATTICE.get(lattice, lattice if isinstance(lattice, int) else -1)

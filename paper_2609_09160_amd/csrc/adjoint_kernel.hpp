@@ -40,7 +40,7 @@ namespace lbf {
 template <int Q_, typename C_, bool FFIELD>
 struct Adjoint {
   static constexpr int Q = Q_;
-  static constexpr bool kThreeSites = false;
+  static constexpr bool kThreeSites = std::is_same_v<C_, float>;
   using C = C_;
   using T = C_;
   // lambda(t+1) and F of a site; destinations also read u(t+1), u(t) and
@@ -192,24 +192,33 @@ struct Adjoint {
 template <typename C>
 hipError_t launch_adjoint_type(int Q, int tile_rows, bool walls_y, bool ffield,
                                const StepArgs& a, hipStream_t s) {
-  if (a.lane_sites != 1) return hipErrorInvalidValue;
-// one site per lane: a destination reads 22 values, two per lane would spill
-#define LBF_ADJ_CASE(QQ, TYY)                                                         \
-  if (Q == QQ && tile_rows == TYY) {                                                 \
+  // A destination reads 22 values: one site per lane fits 10-wave workgroups
+  // (8-row tiles); two or three sites per lane (FP32) need the register room
+  // of shorter tiles (4 or 6 rows: at most 2 waves per SIMD).
+#define LBF_ADJ_CASE(QQ, TYY, SS)                                                     \
+  if (Q == QQ && tile_rows == TYY && a.lane_sites == SS) {                            \
     if (walls_y)                                                                     \
-      return ffield ? launch_march_s<Adjoint<QQ, C, true>, TYY, true, 1>(a, s)       \
-                    : launch_march_s<Adjoint<QQ, C, false>, TYY, true, 1>(a, s);     \
-    return ffield ? launch_march_s<Adjoint<QQ, C, true>, TYY, false, 1>(a, s)        \
-                  : launch_march_s<Adjoint<QQ, C, false>, TYY, false, 1>(a, s);      \
+      return ffield ? launch_march_s<Adjoint<QQ, C, true>, TYY, true, SS>(a, s)      \
+                    : launch_march_s<Adjoint<QQ, C, false>, TYY, true, SS>(a, s);    \
+    return ffield ? launch_march_s<Adjoint<QQ, C, true>, TYY, false, SS>(a, s)       \
+                  : launch_march_s<Adjoint<QQ, C, false>, TYY, false, SS>(a, s);     \
   }
-  LBF_ADJ_CASE(19, 4)
-  LBF_ADJ_CASE(19, 6)
-  LBF_ADJ_CASE(19, 8)
-  LBF_ADJ_CASE(19, 14)
-  LBF_ADJ_CASE(27, 4)
-  LBF_ADJ_CASE(27, 6)
-  LBF_ADJ_CASE(27, 8)
-  LBF_ADJ_CASE(27, 14)
+  LBF_ADJ_CASE(19, 4, 1)
+  LBF_ADJ_CASE(19, 6, 1)
+  LBF_ADJ_CASE(19, 8, 1)
+  LBF_ADJ_CASE(19, 14, 1)
+  LBF_ADJ_CASE(27, 4, 1)
+  LBF_ADJ_CASE(27, 6, 1)
+  LBF_ADJ_CASE(27, 8, 1)
+  LBF_ADJ_CASE(27, 14, 1)
+  if constexpr (std::is_same_v<C, float>) {
+    LBF_ADJ_CASE(19, 4, 2)
+    LBF_ADJ_CASE(19, 6, 2)
+    LBF_ADJ_CASE(19, 4, 3)
+    LBF_ADJ_CASE(19, 6, 3)
+    LBF_ADJ_CASE(27, 4, 2)
+    LBF_ADJ_CASE(27, 4, 3)
+  }
 #undef LBF_ADJ_CASE
   return hipErrorInvalidValue;
 }

@@ -108,8 +108,9 @@ int validate(const lbfast_params* p) {
   }
   for (int k = 0; k < 7; ++k)
     if (p->reserved[k] != 0) return fail(LBF_E_ARG, "reserved[%d] must be zero", k);
-  if (p->rounding != LBF_ROUND_NEAREST && p->rounding != LBF_ROUND_STOCHASTIC)
-    return fail(LBF_E_ARG, "rounding must be LBF_ROUND_NEAREST or LBF_ROUND_STOCHASTIC");
+  if (p->rounding != LBF_ROUND_AUTO && p->rounding != LBF_ROUND_NEAREST &&
+      p->rounding != LBF_ROUND_STOCHASTIC)
+    return fail(LBF_E_ARG, "rounding must be LBF_ROUND_AUTO, _NEAREST or _STOCHASTIC");
   if (p->rounding == LBF_ROUND_STOCHASTIC && !s16)
     return fail(LBF_E_ARG, "stochastic rounding applies to 16-bit storage only");
   return LBF_OK;
@@ -140,6 +141,7 @@ struct lbfast_ctx {
   unsigned* d_maxbits = nullptr; // 10
   int64_t N = 0;
   uint64_t steps_done = 0;       // steps since create: seeds the stochastic rounding
+  int adj_sites = 0, adj_rows = 0;  // adjoint launch shape (0: automatic)
 };
 
 namespace {
@@ -266,7 +268,8 @@ int step_args(const lbfast_ctx* h, lbf::StepArgs* a) {
     a->inv_scale[k] = h->inv_scale[k];
   }
   a->Ffield = h->Ffield;
-  a->stochastic = h->p.rounding == LBF_ROUND_STOCHASTIC;
+  a->stochastic = h->p.rounding == LBF_ROUND_STOCHASTIC ||
+                  (h->p.rounding == LBF_ROUND_AUTO && h->p.storage == LBF_BF16S);
   if (h->two_phase) {
     // the phases' relaxation times replace params.tau
     a->omega = 1.0 / h->pp.tau_l;
@@ -670,6 +673,29 @@ int lbfast_set_lane_sites(lbfast_t h, int sites) {
   return LBF_OK;
 }
 
+int lbfast_set_adjoint_launch(lbfast_t h, int sites, int tile_rows) {
+  g_err.clear();
+  if (int rc = check_handle(h)) return rc;
+  if (sites < 0 || sites > 3) return fail(LBF_E_ARG, "sites must be 0, 1, 2 or 3");
+  if (tile_rows != 0 && tile_rows != 4 && tile_rows != 6 && tile_rows != 8 && tile_rows != 14)
+    return fail(LBF_E_ARG, "tile_rows must be 0, 4, 6, 8 or 14");
+  const int S = sites ? sites : 1;
+  const int ty = tile_rows ? tile_rows : (h->p.storage == LBF_F64 ? 6 : 8);
+  if (S > 1) {
+    if (h->p.storage != LBF_F32)
+      return fail(LBF_E_UNSUPPORTED, "two or three sites per lane: F32 storage only");
+    if ((S == 2 && h->p.nx % 2 != 0) || (S == 3 && h->p.nx % 3 != 0))
+      return fail(LBF_E_UNSUPPORTED, "nx must be divisible by the sites per lane");
+    if (ty > 6 || (h->p.lattice == LBF_D3Q27 && ty != 4) ||
+        (h->p.lattice == LBF_D3Q19 && ty != 4 && ty != 6))
+      return fail(LBF_E_UNSUPPORTED,
+                  "two or three sites per lane: 4- or 6-row tiles (D3Q27: 4 rows)");
+  }
+  h->adj_sites = sites;
+  h->adj_rows = tile_rows;
+  return LBF_OK;
+}
+
 int lbfast_step(lbfast_t h, int64_t n) {
   g_err.clear();
   if (int rc = check_handle(h)) return rc;
@@ -915,11 +941,13 @@ int lbfast_adjoint(lbfast_t h, int64_t nsteps, int64_t every, const void* ckpt_d
   if (int rc = step_args(h, &fa)) return rc;
   aa = fa;
   aa.gF = gF_dev;
-  // The adjoint step reads 22 values per destination site: one site per lane
-  // (two would spill registers), 8-row tiles (FP64: 6)
-  aa.lane_sites = 1;
-  const int adj_rows = (h->p.storage == LBF_F64) ? 6 : 8;
-  if (int rc = resolve_zchunk(h, 1, adj_rows, &aa.tiles_x, &aa.tiles_y, &aa.zchunks, &aa.zchunk))
+  // The adjoint step reads 22 values per destination site: by default one
+  // site per lane and 8-row tiles (FP64: 6); lbfast_set_adjoint_launch may
+  // choose two or three sites per lane with 4- or 6-row tiles (FP32)
+  aa.lane_sites = h->adj_sites ? h->adj_sites : 1;
+  const int adj_rows = h->adj_rows ? h->adj_rows : ((h->p.storage == LBF_F64) ? 6 : 8);
+  if (int rc = resolve_zchunk(h, aa.lane_sites, adj_rows, &aa.tiles_x, &aa.tiles_y, &aa.zchunks,
+                              &aa.zchunk))
     return rc;
   const int64_t nseg = (nsteps + every - 1) / every;
   const bool walls_y = h->p.bc[1] == LBF_WALLS;

@@ -17,14 +17,14 @@ class Solver:
     shape = (nx, ny, nz); lattice in {19, 27, "27h"} ("27h": the D3Q27 set
     with the complete Hermite basis); storage in {"f64", "f32", "f16s", "bf16s"};
     bc = per-axis 0 (periodic) / 1 (walls, y only); force = uniform body force;
-    rounding = "nearest" or "stochastic" (16-bit storage: how the step rounds
-    p* and u).
+    rounding = "auto" (FP16 to nearest, BF16 stochastic), "nearest" or
+    "stochastic" (16-bit storage: how the step rounds p* and u).
     The two flip/flop moment buffers are torch allocations on `device`, the
     launches go to torch's current stream of that device.
     """
 
     def __init__(self, shape, tau, lattice=19, storage="f32", bc=(0, 0, 0),
-                 force=(0.0, 0.0, 0.0), scale=None, device=None, rounding="nearest"):
+                 force=(0.0, 0.0, 0.0), scale=None, device=None, rounding="auto"):
         import torch
         self._torch = torch
         self.lib = _lib.load()
@@ -108,6 +108,10 @@ class Solver:
         if lane_sites:
             check(self.lib.lbfast_set_lane_sites(self.h, int(lane_sites)))
         check(self.lib.lbfast_set_launch(self.h, int(tile_rows), int(z_chunk)))
+
+    def set_adjoint_launch(self, sites=0, tile_rows=0):
+        """Launch shape of the adjoint step (0 = automatic)."""
+        check(self.lib.lbfast_set_adjoint_launch(self.h, int(sites), int(tile_rows)))
 
     def scales(self):
         out = (ctypes.c_float * 10)()

@@ -13,7 +13,7 @@ def say(*a):
 
 
 def gpu_run(shape, tau, m0, steps, lattice=19, storage="f64", bc=(0, 0, 0), force=(0, 0, 0),
-            Ffield=None, launch=None, scale=None, rounding="nearest"):
+            Ffield=None, launch=None, scale=None, rounding="auto"):
     """Run the HIP path; returns host float64 moments [10, nz, ny, nx]."""
     import torch
     from paper_2609_09160_amd import Solver

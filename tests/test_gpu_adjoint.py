@@ -29,7 +29,7 @@ def _flat(a):
 
 
 def gpu_adjoint(shape, tau, m0, F, steps, every, gT, lattice=19, storage="f64", bc=(0, 0, 0),
-                launch=None):
+                launch=None, adj_launch=None):
     """(dJ/dF, dJ/dm0, m(T)) from the HIP path, host float64, [k, N]."""
     import torch
     from paper_2609_09160_amd import Solver
@@ -38,6 +38,8 @@ def gpu_adjoint(shape, tau, m0, F, steps, every, gT, lattice=19, storage="f64", 
     s = Solver(shape, tau, lattice=lattice, storage=storage, bc=bc)
     if launch:
         s.set_launch(*launch)
+    if adj_launch:
+        s.set_adjoint_launch(*adj_launch)
     s.set_force_field(torch.as_tensor(F.reshape(3, nz, ny, nx), device="cuda", dtype=dt))
     s.set_moments(np.ascontiguousarray(m0))
     ckpt = s.forward_checkpointed(steps, every)
@@ -143,6 +145,31 @@ def test_adjoint_fp32_vs_oracle_32(Q):
     say(f"adjoint fp32 vs oracle 32^3 Q{Q}")
     gF, g0, _ = gpu_adjoint(shape, tau, m0, F, steps, 50, r, lattice=Q, storage="f32")
     wF, w0 = A.adjoint(Q, shape, tau, m0, F, steps, r)
+    eF = float(np.linalg.norm(gF - wF) / np.linalg.norm(wF))
+    e0 = float(np.linalg.norm(g0 - w0) / np.linalg.norm(w0))
+    say(f"  rel L2 dJ/dF {eF:.2e}, dJ/dm0 {e0:.2e}")
+    assert eF <= 1e-4 and e0 <= 1e-4
+
+
+@pytest.mark.parametrize("Q,adj_launch", [(19, (3, 4)), (19, (3, 6)), (19, (2, 6)),
+                                          (19, (2, 4)), (27, (3, 4)), (27, (2, 4))])
+@pytest.mark.parametrize("walls", [False, True])
+def test_adjoint_fp32_lane_sites(Q, adj_launch, walls):
+    """Two or three x-sites per lane in the FP32 adjoint step (48 x 13 x 10:
+    one full 96- or 128/192-wide tile or less, ragged y, periodic or y-walls,
+    uniform force field std 1e-4, 30 steps, checkpoints every 7): dJ/dF and
+    dJ/dm0 against the FP64 CPU adjoint, relative L2 <= 1e-4 (the FP32 bar)."""
+    from oracle import adjoint as A
+    shape, tau, steps = (48, 13, 10), 0.8, 30
+    N = shape[0] * shape[1] * shape[2]
+    bc = (0, 1 if walls else 0, 0)
+    m0 = inputs.random_state(shape, seed=70).reshape(10, N)
+    F = inputs.random_force(shape, seed=71, std=1e-4).reshape(3, N)
+    r = np.random.default_rng(72).standard_normal((10, N))
+    say(f"adjoint fp32 Q{Q} adjoint launch {adj_launch} walls={walls}")
+    gF, g0, _ = gpu_adjoint(shape, tau, m0, F, steps, 7, r, lattice=Q, storage="f32", bc=bc,
+                            adj_launch=adj_launch)
+    wF, w0 = A.adjoint(Q, shape, tau, m0, F, steps, r, bc=bc)
     eF = float(np.linalg.norm(gF - wF) / np.linalg.norm(wF))
     e0 = float(np.linalg.norm(g0 - w0) / np.linalg.norm(w0))
     say(f"  rel L2 dJ/dF {eF:.2e}, dJ/dm0 {e0:.2e}")

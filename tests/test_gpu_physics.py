@@ -52,13 +52,15 @@ def test_storage_forms_512_vs_fp64(Q):
     a2 - u u are two orders smaller): FP16 with rounding to nearest about
     2.5e-3 and with stochastic rounding about 1.5e-3, i.e. above the 1e-3
     bar stated for 16-bit storage, which FP16 meets on the faster 64^3
-    field; BF16 about 1e-2."""
+    field; BF16 (stochastic, its default) about 1e-2 -- rounded to nearest,
+    its 8-bit significand drops almost every change of this field and the
+    error reaches 0.2."""
     import torch
     from paper_2609_09160_amd import Solver
     n, steps = 512, 1000
     m0 = inputs.solenoidal_field((n, n, n), device="cuda")
 
-    def u_after(storage, rounding="nearest"):
+    def u_after(storage, rounding="auto"):
         s = Solver((n, n, n), 0.6, lattice=Q, storage=storage, rounding=rounding)
         s.set_moments(m0)
         s.step(steps)
@@ -77,8 +79,8 @@ def test_storage_forms_512_vs_fp64(Q):
     s.close()
     torch.cuda.empty_cache()
     ref_norm = float(torch.linalg.vector_norm(ref))
-    bars = {("f32", "nearest"): 1e-5, ("f16s", "nearest"): 4e-3, ("f16s", "stochastic"): 2.5e-3,
-            ("bf16s", "nearest"): 3e-2}
+    bars = {("f32", "auto"): 1e-5, ("f16s", "nearest"): 4e-3, ("f16s", "stochastic"): 2.5e-3,
+            ("bf16s", "stochastic"): 3e-2}
     for (storage, rounding), bar in bars.items():
         u = u_after(storage, rounding)
         e = float(torch.linalg.vector_norm(u - ref)) / ref_norm

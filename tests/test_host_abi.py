@@ -82,8 +82,8 @@ def _create(lib, p, bufs=(None, None)):
     (lambda p: (setattr(p, "storage", 2), p.scale.__setitem__(3, 3.0)), _lib.LBF_E_ARG,
      "power of two"),
     (lambda p: p.reserved.__setitem__(2, 1), _lib.LBF_E_ARG, "reserved"),
-    (lambda p: setattr(p, "rounding", 2), _lib.LBF_E_ARG, "rounding"),
-    (lambda p: setattr(p, "rounding", 1), _lib.LBF_E_ARG, "16-bit storage only"),
+    (lambda p: setattr(p, "rounding", 3), _lib.LBF_E_ARG, "rounding"),
+    (lambda p: setattr(p, "rounding", 2), _lib.LBF_E_ARG, "16-bit storage only"),
     (lambda p: p.force.__setitem__(1, float("inf")), _lib.LBF_E_ARG, "force"),
 ])
 def test_validation_before_device(lib, mutate, code, needle):
