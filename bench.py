@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, AMD published peak
 BYTES_PER_VALUE = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
 CSRC = os.path.join(ROOT, "paper_2609_09160_amd", "csrc")
 KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("march.hpp", "step_kernel.hpp", "lattice.hpp",
-                                                "internal.hpp", "step_f32.hip")]
+                                                "stencil.hpp", "internal.hpp", "step_f32.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_d3q19_f32_512.txt")
 
 
@@ -198,31 +198,36 @@ def stream_ceiling(n=512 ** 3, nplanes=10, reps=5):
     return nbytes / (ms * 1e-3) / 1e9, ms, nbytes
 
 
-def copy_ceiling(n=512 ** 3, nplanes=10, reps=5):
-    """The fastest copy form measured on MI355X (one 16-byte access per lane,
-    non-temporal stores) over nplanes x n floats: GB/s counting read + write,
-    the ceiling of a stream that reads and writes equal volumes."""
+def copy_ceiling(n=512 ** 3, nplanes=10, reps=5, planes=False):
+    """Best-of-reps GB/s (read + write) of one of the library's two copy
+    probes over nplanes x n floats: the one-shot 16-byte copy (the fastest
+    copy form measured on MI355X) or, with planes=True, the ten-plane copy
+    (the step's own load/store pattern, no halos, no arithmetic)."""
     import ctypes
     import torch
     from paper_2609_09160_amd import _lib
     lib = _lib.load()
-    a = torch.ones(nplanes * n, dtype=torch.float32, device="cuda")
+    a = torch.rand(nplanes * n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     stream = torch.cuda.current_stream()
-    args = (ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), nplanes * n // 4,
-            ctypes.c_void_p(stream.cuda_stream))
-    _lib.check(lib.lbfast_copy_probe(*args))
+    A, B, S = (ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+               ctypes.c_void_p(stream.cuda_stream))
+    if planes:
+        run = lambda: _lib.check(lib.lbfast_planes_probe(A, B, n, nplanes, S))  # noqa: E731
+    else:
+        run = lambda: _lib.check(lib.lbfast_copy_probe(A, B, nplanes * n // 4, S))  # noqa: E731
+    run()
     torch.cuda.synchronize()
     best = None
     for _ in range(reps):
         st, en = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         st.record(stream)
-        _lib.check(lib.lbfast_copy_probe(*args))
+        run()
         en.record(stream)
         torch.cuda.synchronize()
         ms = st.elapsed_time(en)
         best = ms if best is None else min(best, ms)
-    assert torch.equal(a[-1024:], b[-1024:])
+    assert torch.equal(a, b)
     del a, b
     torch.cuda.empty_cache()
     return 2 * 4 * nplanes * n / (best * 1e-3) / 1e9
@@ -257,11 +262,13 @@ def copy_ceilings(n=512 ** 3, nplanes=10, reps=10):
             t = ms if t is None else min(t, ms)
         return round(nbytes / (t * 1e-3) / 1e9, 1)
 
-    probe = lambda: _lib.check(lib.lbfast_copy_probe(  # noqa: E731
-        ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), nplanes * n // 4,
-        ctypes.c_void_p(stream.cuda_stream)))
+    A, B, S = (ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+               ctypes.c_void_p(stream.cuda_stream))
+    probe = lambda: _lib.check(lib.lbfast_copy_probe(A, B, nplanes * n // 4, S))  # noqa: E731
+    planes = lambda: _lib.check(lib.lbfast_planes_probe(A, B, n, nplanes, S))  # noqa: E731
     out = {"bytes_read": nbytes // 2, "bytes_written": nbytes // 2,
            "library_copy_probe_GBs": best(probe),
+           "library_planes_probe_GBs": best(planes),
            "torch_copy_GBs": best(lambda: b.copy_(a)),
            "torch_elementwise_GBs": best(lambda: torch.mul(a, 1.0, out=b))}
     assert torch.equal(a[-4096:], b[-4096:])
@@ -348,11 +355,10 @@ def run_adjoint(n=192, steps=500, reps=2):
             "finite": fin1 and fin50}
 
 
-TP_BYTES_PER_LUP = 140  # two-component step, FP32: fused step with F(t) and F(t+1) 104;
-                        # phase update 20 (phi, u in; phi out); capillary force 16 (phi
-                        # in, F out)
-TP_CONTRAST_EXTRA = 48  # with density contrast: phi(t), phi(t+1) read by the fused step 8;
-                        # the force pass reads the 10 moments of the state 40
+TP_BYTES_PER_LUP = 128  # two-component step, FP32: the fused step 108 (moments 40, F(t) 12
+                        # and phi(t+1) 4 in; moments 40 and F(t+1) 12 out); the phase
+                        # update 20 (phi, u in; phi out)
+TP_CONTRAST_EXTRA = 4   # with density contrast: phi(t), read by the fused step
 
 
 def run_two_phase(n=256, steps=100, warmup=10, storage="f32", contrast=False):
@@ -567,6 +573,9 @@ def main():
     cgbs = copy_ceiling()
     out["roofline"]["measured_copy_GBs"] = round(cgbs, 1)
     out["roofline"]["frac_of_measured_copy"] = round(achieved / cgbs, 4)
+    pgbs = copy_ceiling(planes=True)
+    out["roofline"]["measured_ten_plane_copy_GBs"] = round(pgbs, 1)
+    out["roofline"]["frac_of_ten_plane_copy"] = round(achieved / pgbs, 4)
     # (lattice, storage, rounding of p* and u; "auto": FP16 to nearest, BF16 stochastic)
     VARIANTS = ((27, "f32", "auto"), (19, "f16s", "auto"), (19, "f16s", "stochastic"),
                 (19, "bf16s", "auto"), (27, "f16s", "auto"), (19, "f64", "auto"),

@@ -22,11 +22,19 @@ extern "C" {
 int lbfast_stream_probe(const void* src, void* dst, int64_t n, int nplanes, void* stream);
 
 /* Measurement utility, not part of the method: copy n4 16-byte elements from
- * src to dst (device pointers, 16-byte aligned) on `stream` with one 16-byte
- * access per lane and non-temporal stores, the fastest copy form measured on
- * MI355X: the bandwidth ceiling of a stream that reads and writes equal
- * volumes, against which the step's achieved bandwidth is set. */
+ * src to dst (device pointers, 16-byte aligned) on `stream`, one 16-byte
+ * access per thread in a one-shot grid, non-temporal stores: the fastest
+ * copy form measured on MI355X, the bandwidth ceiling of a single stream that
+ * reads and writes equal volumes. */
 int lbfast_copy_probe(const void* src, void* dst, int64_t n4, void* stream);
+
+/* Measurement utility, not part of the method: copy nplanes (1..10) planes
+ * of n floats (n even) in structure of arrays from src to dst (device
+ * pointers, 8-byte aligned), each thread moving two consecutive floats of
+ * every plane (all loads, then all non-temporal stores): the step's load and
+ * store pattern without halos or arithmetic, the ceiling the step is set
+ * against. */
+int lbfast_planes_probe(const void* src, void* dst, int64_t n, int nplanes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -86,6 +86,7 @@ def load():
         "lbfast_last_error": ([], ctypes.c_char_p),
         "lbfast_stream_probe": ([vp, vp, i64, i32, vp], i32),
         "lbfast_copy_probe": ([vp, vp, i64, vp], i32),
+        "lbfast_planes_probe": ([vp, vp, i64, i32, vp], i32),
         "lbfast_enable_two_phase": ([vp, ctypes.POINTER(LbfastPhaseParams)], i32),
         "lbfast_set_phase": ([vp, vp, i32, i32], i32),
         "lbfast_get_phase": ([vp, vp, i32, i32], i32),
@@ -95,6 +96,8 @@ def load():
         "lbfast_set_adjoint_launch": ([vp, i32, i32], i32),
     }
     for name, (args, res) in sig.items():
+        if path != LIB_PATH and not hasattr(lib, name):
+            continue  # an alternate build may predate a symbol
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = res

@@ -41,6 +41,7 @@ template <int Q_, typename C_, bool FFIELD>
 struct Adjoint {
   static constexpr int Q = Q_;
   static constexpr bool kThreeSites = std::is_same_v<C_, float>;
+  static constexpr bool kStencil = false;
   using C = C_;
   using T = C_;
   // lambda(t+1) and F of a site; destinations also read u(t+1), u(t) and

@@ -218,14 +218,31 @@ __global__ void stream_probe_kernel(const float* __restrict__ src, float* __rest
   }
 }
 
-// One 16-byte access per lane per trip, non-temporal stores, 1024 x 256
-// threads: the fastest form of a copy measured on MI355X, i.e. the ceiling for
-// a stream that reads and writes equal volumes.
+// One 16-byte access per lane and one per thread (a one-shot grid of
+// 256-thread blocks), non-temporal stores: the fastest form of a copy
+// measured on MI355X (6.2-6.3 TB/s; grid-stride forms reach 5.3), i.e. the
+// ceiling of a single stream that reads and writes equal volumes.
 typedef float F4 __attribute__((ext_vector_type(4)));
+typedef float F2 __attribute__((ext_vector_type(2)));
 __global__ void copy_wide_kernel(const F4* __restrict__ src, F4* __restrict__ dst, int64_t n4) {
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n4;
-       i += static_cast<int64_t>(gridDim.x) * kThreads)
-    __builtin_nontemporal_store(src[i], &dst[i]);
+  const int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+  if (i < n4) __builtin_nontemporal_store(src[i], &dst[i]);
+}
+
+// The step's access pattern without halos or arithmetic: nplanes planes of n
+// floats in structure of arrays, each thread reading 8 bytes (two consecutive
+// floats) from every plane and then writing them, non-temporal stores.
+template <int NPL>
+__global__ void __launch_bounds__(kThreads) copy_planes_kernel(const float* __restrict__ src,
+                                                               float* __restrict__ dst, int64_t n) {
+  const int64_t i = (blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x) * 2;
+  if (i >= n) return;
+  F2 v[NPL];
+#pragma unroll
+  for (int k = 0; k < NPL; ++k) v[k] = *reinterpret_cast<const F2*>(src + k * n + i);
+#pragma unroll
+  for (int k = 0; k < NPL; ++k)
+    __builtin_nontemporal_store(v[k], reinterpret_cast<F2*>(dst + k * n + i));
 }
 
 Scales to_scales(const float* p) {
@@ -320,8 +337,35 @@ hipError_t launch_stream_probe(const void* src, void* dst, int64_t n, int nplane
 }
 
 hipError_t launch_copy_probe(const void* src, void* dst, int64_t n4, hipStream_t s) {
-  hipLaunchKernelGGL(copy_wide_kernel, dim3(1024), dim3(kThreads), 0, s,
+  const int64_t blocks = (n4 + kThreads - 1) / kThreads;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(copy_wide_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, s,
                      static_cast<const F4*>(src), static_cast<F4*>(dst), n4);
+  return hipGetLastError();
+}
+
+hipError_t launch_planes_probe(const void* src, void* dst, int64_t n, int nplanes, hipStream_t s) {
+  const int64_t blocks = (n / 2 + kThreads - 1) / kThreads;
+  if (blocks > 0x7fffffff || nplanes < 1 || nplanes > 10 || n % 2) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>(blocks));
+  const float* a = static_cast<const float*>(src);
+  float* b = static_cast<float*>(dst);
+  auto go = [&](auto NPL) {
+    hipLaunchKernelGGL(copy_planes_kernel<decltype(NPL)::value>, grid, dim3(kThreads), 0, s, a, b,
+                       n);
+  };
+  switch (nplanes) {
+    case 1: go(std::integral_constant<int, 1>{}); break;
+    case 2: go(std::integral_constant<int, 2>{}); break;
+    case 3: go(std::integral_constant<int, 3>{}); break;
+    case 4: go(std::integral_constant<int, 4>{}); break;
+    case 5: go(std::integral_constant<int, 5>{}); break;
+    case 6: go(std::integral_constant<int, 6>{}); break;
+    case 7: go(std::integral_constant<int, 7>{}); break;
+    case 8: go(std::integral_constant<int, 8>{}); break;
+    case 9: go(std::integral_constant<int, 9>{}); break;
+    default: go(std::integral_constant<int, 10>{}); break;
+  }
   return hipGetLastError();
 }
 

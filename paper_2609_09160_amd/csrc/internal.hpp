@@ -16,18 +16,24 @@ struct StepArgs {
   const void* src;     // current moment buffer (10 planes)
   void* dst;           // next moment buffer (10 planes)
   const void* Ffield;  // 3 planes of the compute type, or nullptr (uniform F)
-  const void* Fnext;   // force of the next time level for the correction, or
-                       // nullptr (static force: Ffield serves both)
-  // two-component flow with density and viscosity contrast (else nullptr):
-  // phase field at t (sources) and t+1 (destinations), N values of the
-  // compute type; rho = rho_l + phi (rho_h - rho_l), likewise nu
-  const void* phi_src;
+  // Two-component flow (else nullptr): Ffield holds F(t); the step computes
+  // F(t+1) from phi(t+1) (phi_dst, N values of the compute type) at each
+  // destination, uses it in the correction and writes it to Fout (3 planes).
+  // F = mu grad(phi) + rho(phi) Fb, mu = 4 beta phi (phi - 1)(phi - 1/2) -
+  // kappa lap(phi); with `contrast` also the pressure and viscous terms.
+  void* Fout;
   const void* phi_dst;
+  double beta, kappa, Fb[3];
+  int contrast;
+  // variable density and viscosity (else nullptr): phi(t) at the sources;
+  // rho = rho_l + phi (rho_h - rho_l), likewise nu
+  const void* phi_src;
   double rho_l, rho_h, nu_l, nu_h;
   int nx, ny, nz;
   int64_t N;           // plane stride = nx*ny*nz
   int tiles_x, tiles_y, zchunks, zchunk;
-  int lane_sites;      // consecutive x-sites per lane: 1, or 2 (even nx; tile width 128)
+  int lane_sites;      // consecutive x-sites per lane: 1, 2 or 3 (tile width 64, 128, 192)
+  int xcd_remap;       // give each XCD a contiguous range of tiles (else hardware order)
   double omega;
   double F[3];         // uniform force (used when Ffield == nullptr)
   float scale[10];     // 16-bit storage: value = scale * q

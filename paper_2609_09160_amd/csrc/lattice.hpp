@@ -109,14 +109,11 @@ constexpr int kD3Q27H = 270;
 // hardware range check against the plane size turns any out-of-range offset
 // into a zero load / dropped store instead of a fault.
 constexpr int kBufWord3 = 0x00020000;  // gfx9 family: 32-bit data format, raw access
-#ifndef LBF_STORE_CPOL
-#define LBF_STORE_CPOL 2
-#endif
-constexpr int kNonTemporal = LBF_STORE_CPOL;  // cache policy of the plane stores (2: nt)
-#ifndef LBF_LOAD_CPOL
-#define LBF_LOAD_CPOL 0
-#endif
-constexpr int kLoadCpol = LBF_LOAD_CPOL;  // cache policy of the plane loads (0: default)
+// Cache policies of the plane accesses: non-temporal stores (2) and default
+// loads (0).  Measured on MI355X at 512^3 FP32: plain stores 3.5% slower,
+// non-temporal loads 34% slower (the halo re-reads then miss the caches).
+constexpr int kNonTemporal = 2;
+constexpr int kLoadCpol = 0;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), static_cast<short>(0),

@@ -17,8 +17,9 @@
 #include "internal.hpp"
 
 namespace lbf {
-// measurement utility, aux.hip
+// measurement utilities, aux.hip
 hipError_t launch_copy_probe(const void* src, void* dst, int64_t n4, hipStream_t s);
+hipError_t launch_planes_probe(const void* src, void* dst, int64_t n, int nplanes, hipStream_t s);
 }  // namespace lbf
 
 namespace {
@@ -148,10 +149,19 @@ namespace {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Block order of the adjoint step: contiguous tile ranges per XCD (1) or the
+// hardware order (0); the forward step uses the hardware order, measured
+// as fast for FP32 and faster for 16-bit storage at 512^3.
+#ifndef LBF_ADJOINT_XCD_REMAP
+#define LBF_ADJOINT_XCD_REMAP 1
+#endif
+
 // LDS of one step workgroup: staged populations x (rows + 2) x (64 S + 2)
 // columns, plus the x-halo column buffer
-size_t lds_bytes(int Q, int storage, int tile_rows, int lane_sites) {
-  const size_t np = (Q == LBF_D3Q19) ? 16 : 24;
+// LDS of one step workgroup; the two-component step stages phi(t+1) in one
+// more slot for its stencils
+size_t lds_bytes(int Q, int storage, int tile_rows, int lane_sites, bool stencil = false) {
+  const size_t np = ((Q == LBF_D3Q19) ? 16 : 24) + (stencil ? 1 : 0);
   const size_t c = (storage == LBF_F64) ? 8 : 4;
   return c * np * static_cast<size_t>(tile_rows + 2) * static_cast<size_t>(64 * lane_sites + 4);
 }
@@ -378,6 +388,18 @@ int lbfast_copy_probe(const void* src, void* dst, int64_t n4, void* stream) {
   if (n4 < 1) return fail(LBF_E_ARG, "n4 must be >= 1");
   hipError_t e = lbf::launch_copy_probe(src, dst, n4, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "copy probe");
+  return LBF_OK;
+}
+
+int lbfast_planes_probe(const void* src, void* dst, int64_t n, int nplanes, void* stream) {
+  g_err.clear();
+  if (!src || !dst) return fail(LBF_E_ARG, "null buffer");
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 7)
+    return fail(LBF_E_ARG, "buffers must be 8-byte aligned");
+  if (n < 2 || n % 2) return fail(LBF_E_ARG, "n must be even and >= 2");
+  if (nplanes < 1 || nplanes > 10) return fail(LBF_E_ARG, "nplanes must be in [1, 10]");
+  hipError_t e = lbf::launch_planes_probe(src, dst, n, nplanes, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "planes probe");
   return LBF_OK;
 }
 
@@ -635,7 +657,7 @@ int lbfast_set_launch(lbfast_t h, int tile_rows, int z_chunk) {
       return fail(LBF_E_UNSUPPORTED, "two or three x-sites per lane support tiles of at most 8 rows");
     if (h->p.lattice == LBF_D3Q27H && tile_rows > 8)
       return fail(LBF_E_UNSUPPORTED, "D3Q27h supports tiles of at most 8 rows");
-    const size_t lb = lds_bytes(h->p.lattice, h->p.storage, tile_rows, h->lane_sites);
+    const size_t lb = lds_bytes(h->p.lattice, h->p.storage, tile_rows, h->lane_sites, h->two_phase);
     if (lb > kLdsLimit)
       return fail(LBF_E_UNSUPPORTED, "tile_rows %d needs %zu bytes of LDS (limit 160 KiB)",
                   tile_rows, lb);
@@ -659,10 +681,11 @@ int lbfast_set_lane_sites(lbfast_t h, int sites) {
                 "set and one component");
   // keep the tile height if it fits, else the tallest one (of 8, 6, 4) that does
   int ty = h->tile_rows;
-  if ((sites >= 2 && ty > 8) || lds_bytes(h->p.lattice, h->p.storage, ty, sites) > kLdsLimit) {
+  if ((sites >= 2 && ty > 8) ||
+      lds_bytes(h->p.lattice, h->p.storage, ty, sites, h->two_phase) > kLdsLimit) {
     ty = 0;
     for (int t : {8, 6, 4})
-      if (lds_bytes(h->p.lattice, h->p.storage, t, sites) <= kLdsLimit) {
+      if (lds_bytes(h->p.lattice, h->p.storage, t, sites, h->two_phase) <= kLdsLimit) {
         ty = t;
         break;
       }
@@ -710,17 +733,18 @@ int lbfast_step(lbfast_t h, int64_t n) {
     a.dst = h->buf[h->cur ^ 1];
     a.sr_seed = step_seed(h->steps_done++);
     if (h->two_phase) {
-      // phi(t+1) and F(t+1) first: the correction needs the new force
+      // phi(t+1) first: the step computes F(t+1) from it for the correction
       lbf::PhaseArgs pa = phase_args(h);
       hipError_t e = lbf::launch_phase_step(h->p.storage, pa, h->stream);
-      if (e == hipSuccess) e = lbf::launch_capillary_force(h->p.storage, pa, h->stream);
       if (e != hipSuccess) return hip_fail(e, "phase-field launch");
       a.Ffield = h->Fph[h->pcur];
-      a.Fnext = h->Fph[h->pcur ^ 1];
-      if (variable_properties(h)) {
-        a.phi_src = h->phi[h->pcur];
-        a.phi_dst = h->phi[h->pcur ^ 1];
-      }
+      a.Fout = h->Fph[h->pcur ^ 1];
+      a.phi_dst = h->phi[h->pcur ^ 1];
+      a.beta = pa.beta;
+      a.kappa = pa.kappa;
+      for (int k = 0; k < 3; ++k) a.Fb[k] = pa.Fb[k];
+      a.contrast = pa.contrast;
+      if (variable_properties(h)) a.phi_src = h->phi[h->pcur];
     }
     if (int rc = launch_forward(h, a)) return rc;
     h->cur ^= 1;
@@ -772,11 +796,19 @@ int lbfast_enable_two_phase(lbfast_t h, const lbfast_phase_params* pp) {
   h->pp = *pp;
   h->two_phase = true;
   h->pcur = 0;
-  if (h->lane_sites == 3) {
-    // the two-component step has one- and two-site forms only
-    h->lane_sites = 1;
-    for (int ty : {8, 6, 4})
-      if (lds_bytes(h->p.lattice, h->p.storage, ty, 1) <= kLdsLimit) {
+  // The two-component step has one- and two-site forms of at most 8 rows,
+  // with one more LDS slot (phi(t+1)) than the one-component step.  With
+  // variable density or viscosity, one site per lane: the two-site form
+  // spills registers there (measured at 256^3 FP32: 0.80 ms against 0.57).
+  const bool one_site = h->lane_sites == 3 || (h->lane_sites == 2 && variable_properties(h));
+  const bool reshape = one_site || h->tile_rows > 8 ||
+                       lds_bytes(h->p.lattice, h->p.storage, h->tile_rows, h->lane_sites,
+                                 true) > kLdsLimit;
+  if (one_site) h->lane_sites = 1;
+  if (reshape) {
+    h->tile_rows = 4;
+    for (int ty : {8, 6})
+      if (lds_bytes(h->p.lattice, h->p.storage, ty, h->lane_sites, true) <= kLdsLimit) {
         h->tile_rows = ty;
         break;
       }
@@ -945,6 +977,7 @@ int lbfast_adjoint(lbfast_t h, int64_t nsteps, int64_t every, const void* ckpt_d
   // site per lane and 8-row tiles (FP64: 6); lbfast_set_adjoint_launch may
   // choose two or three sites per lane with 4- or 6-row tiles (FP32)
   aa.lane_sites = h->adj_sites ? h->adj_sites : 1;
+  aa.xcd_remap = LBF_ADJOINT_XCD_REMAP;
   const int adj_rows = h->adj_rows ? h->adj_rows : ((h->p.storage == LBF_F64) ? 6 : 8);
   if (int rc = resolve_zchunk(h, aa.lane_sites, adj_rows, &aa.tiles_x, &aa.tiles_y, &aa.zchunks,
                               &aa.zchunk))

@@ -23,6 +23,12 @@
 //                             need the directions that enter the tile
 //   P::finish<S>(a, sums[S], carry[S], pb, off, plane_bytes)   store S
 //                             consecutive destinations
+//   P::kStencil               the destinations also need the gradient and
+//                             Laplacian of a scalar field (stencil.hpp):
+//                             every source site hands P::scalar(raw), the
+//                             skeleton stages it in LDS beside the values,
+//                             accumulates the stencils along z and passes
+//                             them to P::finish<S>(a, sums, carry, st[S], ...)
 //
 // gfx950 mapping (own design; the paper's 8x8x8 shared-memory tiles are prior
 // art for another GPU):
@@ -39,8 +45,9 @@
 //     one plane, the ones with c_z=-1 complete the previous plane, so each
 //     input is read from HBM once per update (plus L2-resident halos) and each
 //     output written once, with no population array anywhere;
-//   * block ids are remapped so that each XCD (own L2) gets a contiguous range
-//     of tiles, y-neighbours first: concurrently running tiles share halo rows.
+//   * block ids can be remapped so that each XCD (own L2) gets a contiguous
+//     range of tiles, y-neighbours first (a.xcd_remap); measured at 512^3 the
+//     plain order is as fast for FP32 and faster for 16-bit storage.
 #pragma once
 
 #ifndef LBF_PREFETCH_DEPTH
@@ -49,6 +56,7 @@
 
 #include "internal.hpp"
 #include "lattice.hpp"
+#include "stencil.hpp"
 
 namespace lbf {
 
@@ -149,21 +157,26 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
   constexpr int W = TW + 2;       // LDS columns: the tile plus the two x-halo columns
   __shared__ C lds[NP][R][W];
   __shared__ C colbuf[NP][2][R];  // next plane's x-halo columns (halo waves)
+  // the stencil's scalar of the source plane, and of the next plane's x-halo
+  // columns (same rows and columns as the staged values)
+  constexpr bool KS = P::kStencil;
+  __shared__ C sgl[KS ? R : 1][KS ? W : 1];
+  __shared__ C sgcol[KS ? 2 : 1][KS ? R : 1];
 
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;  // LDS row of this wave's sites
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const int64_t plane = static_cast<int64_t>(nx) * ny;
 
-  // Hardware hands consecutive block ids to the 8 XCDs in turn; give each XCD
-  // a contiguous range of logical tiles (y fastest, then x, then z chunk).
+  // Logical tile order: y fastest, then x, then z chunk.  Hardware hands
+  // consecutive block ids to the 8 XCDs in turn; with a.xcd_remap each XCD
+  // gets a contiguous range of tiles instead (y-neighbours on one L2).
   const int nb = static_cast<int>(gridDim.x), b0 = static_cast<int>(blockIdx.x);
-#ifndef LBF_NO_XCD_REMAP
-  const int q8 = nb >> 3, r8 = nb & 7, xcd = b0 & 7;
-  int b = xcd * q8 + (xcd < r8 ? xcd : r8) + (b0 >> 3);
-#else
-  int b = b0 + 0 * nb;
-#endif
+  int b = b0;
+  if (a.xcd_remap) {
+    const int q8 = nb >> 3, r8 = nb & 7, xcd = b0 & 7;
+    b = xcd * q8 + (xcd < r8 ? xcd : r8) + (b0 >> 3);
+  }
   const int tyi = b % a.tiles_y;
   b /= a.tiles_y;
   const int txi = b % a.tiles_x;
@@ -239,7 +252,7 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
   // stay in registers (gc).
   constexpr int NU = (Q == 19) ? 5 : 9;  // directions with c_z = +1
   auto body_interior = [&](const int zs, Sums<C> (&acc)[S], C (&up)[S][NU], Carry (&cd)[S],
-                           RawOwn (&rc)[S], RawOwn (&rn)[S],
+                           StencilRoll<C> (&sr)[S], RawOwn (&rc)[S], RawOwn (&rn)[S],
                            const int ahead) __attribute__((always_inline)) {
     // unconditional (the last planes of a chunk fetch unused planes): a
     // conditional fetch makes the wait-count merge stall on the fresh loads
@@ -251,6 +264,7 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
       C g[Q];
       P::template source<true, kSelAll>(a, rc[s], g, cs[s]);
       stage(SelAll{}, g, wv, S * lane + s + 1);
+      if constexpr (KS) sgl[wv][S * lane + s + 1] = P::scalar(rc[s]);
       gc[s][0] = g[L::kRest];
       gc[s][1] = g[L::kUp];
       gc[s][2] = g[L::kDown];
@@ -279,7 +293,23 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
       const bool live = zs - 1 >= z0 && zs - 1 < z1;
       const int64_t pb = static_cast<int64_t>(live ? zs - 1 : z0) * plane;
       const uint32_t off = (store_ok && live) ? off_d : plane_bytes;
-      P::template finish<S>(a, acc, cd, pb, off, plane_bytes);
+      if constexpr (KS) {
+        // this plane's 3 x 3 windows complete the stencils of plane zs - 1
+        StencilOut<C> so[S];
+        static_for<S>([&](auto SI) {
+          constexpr int s = decltype(SI)::value;
+          const int col = S * lane + s;
+          C n[3][3];
+#pragma unroll
+          for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) n[dy][dx] = sgl[wv - 1 + dy][col + dx];
+          so[s] = sr[s].plane(n);
+        });
+        P::template finish<S>(a, acc, cd, so, pb, off, plane_bytes);
+      } else {
+        P::template finish<S>(a, acc, cd, pb, off, plane_bytes);
+      }
     }
     static_for<S>([&](auto SI) {
       constexpr int s = decltype(SI)::value;
@@ -342,11 +372,13 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
     C g[Q];
     Carry cs;
     P::template source<false, cs_sel>(a, r, g, cs);
-    if (do_halo)
+    if (do_halo) {
       static_for<NP>([&](auto I) {
         constexpr int i = decltype(I)::value;
         if constexpr (selected_dir<Q, cs_sel>(i)) colbuf[i][hwave][lane] = g[i];
       });
+      if constexpr (KS) sgcol[hwave][lane] = P::scalar(r);
+    }
   };
   // rc: this plane's row sites, rn: receives plane zs+ahead; hc: the column
   // site of plane zs+1, refilled after use with plane zs+1+U
@@ -354,17 +386,20 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
                        RawHalo (&hc)[1], const int ahead) __attribute__((always_inline)) {
     constexpr int rs_sel = decltype(RS)::value, cs_sel = decltype(CS)::value;
     fetch_row(zs + ahead, off_s, rn);
-    if (do_halo)
+    if (do_halo) {
       static_for<NP>([&](auto I) {
         constexpr int i = decltype(I)::value;
         if constexpr (selected_dir<Q, cs_sel>(i)) lds[i][lane][hcol] = colbuf[i][hwave][lane];
       });
+      if constexpr (KS) sgl[lane][hcol] = sgcol[hwave][lane];
+    }
     static_for<S>([&](auto SI) {
       constexpr int s = decltype(SI)::value;
       C g[Q];
       Carry cs;
       P::template source<false, rs_sel>(a, rc[s], g, cs);
       stage(RS, g, wv, S * lane + s + 1);
+      if constexpr (KS) sgl[wv][S * lane + s + 1] = P::scalar(rc[s]);
     });
     __syncthreads();
     col_to_buf(CS, hc[0]);
@@ -386,10 +421,12 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
     Sums<C> acc[S];
     C up[S][NU];
     Carry cd[S];
+    StencilRoll<C> sr[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       zero(acc[s]);
       P::clear(cd[s]);
+      sr[s].clear();
 #pragma unroll
       for (int u = 0; u < NU; ++u) up[s][u] = C(0);
     }
@@ -400,7 +437,7 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
       const int zb = z0 - 1 + t * U;
       static_for<U>([&](auto K) {
         constexpr int k = decltype(K)::value;
-        body_interior(zb + k, acc, up, cd, rr[k], rr[(k + PF) % U], PF);
+        body_interior(zb + k, acc, up, cd, sr, rr[k], rr[(k + PF) % U], PF);
       });
     }
   } else {
@@ -432,16 +469,17 @@ __global__ void __launch_bounds__(64 * (TY + 2)) march_kernel(const StepArgs a) 
 }
 
 // LDS bytes of one workgroup: NP staged values x (TY+2) rows x (64 S + 2)
-// columns, plus the x-halo column buffer (NP x 2 x (TY+2))
-template <int Q, typename C, int TY, int S>
+// columns, plus the x-halo column buffer (NP x 2 x (TY+2)); a stencil's
+// scalar takes one more such slot
+template <int Q, typename C, int TY, int S, bool KS = false>
 constexpr size_t march_lds_bytes() {
-  return sizeof(C) * Lat<Q>::NP * (TY + 2) * (64 * S + 2 + 2);
+  return sizeof(C) * (Lat<Q>::NP + (KS ? 1 : 0)) * (TY + 2) * (64 * S + 2 + 2);
 }
 constexpr size_t kLdsLimit = 160 * 1024;
 
 template <class P, int TY, bool WALLY, int S>
 hipError_t launch_march_s(const StepArgs& a, hipStream_t stream) {
-  if constexpr (march_lds_bytes<P::Q, typename P::C, TY, S>() > kLdsLimit) {
+  if constexpr (march_lds_bytes<P::Q, typename P::C, TY, S, P::kStencil>() > kLdsLimit) {
     return hipErrorInvalidConfiguration;
   } else {
     const int nb = a.tiles_x * a.tiles_y * a.zchunks;

@@ -10,60 +10,26 @@
 // Eq. (6)).  Halfway walls in y take mirror images for the stencils, the
 // flux normal to the wall reversed.
 //
-// Derivatives use the D3Q27-weighted stencils of section 2 (weights
-// k_i / 216 with k = 64, 16, 4, 1 for |c|^2 = 0..3):
-//   grad_a Psi = (1/cs^2) sum_i w_i c_ia Psi(x + c_i)   = (1/72) sum k_i c_ia Psi_i
-//   lap Psi    = (2/cs^2) sum_{i!=0} w_i (Psi_i - Psi_0) = (1/36) sum k_i (Psi_i - Psi_0)
-//   div V      = (1/cs^2) sum_i w_i c_i . V(x + c_i)
-// (the printed Laplacian stencil is garbled; this is its Taylor-consistent
-// reading, zero on constants).  Periodic grid.
+// Derivatives use the D3Q27-weighted stencils of section 2 (stencil.hpp),
+// and div V = (1/cs^2) sum_i w_i c_i . V(x + c_i).  Periodic grid.
 //
 // One z-march advances phi: it computes the total flux V = phi u + lambda J
 // (J the normalised compression flux) on the fly, keeping the tile's records
 // in LDS, and then phi' = phi - div(V) + D lap(phi).  A second march gives
-// the force from phi(t+1).  Algorithmic traffic at FP32: the phase update
-// 20 B per lattice update (phi, u in; phi out), the force 16 B (phi in, F
-// out), against the fused step's 104.
+// the force of a phase field that is set from outside (the first F(t)); while
+// stepping, the fused step computes F(t+1) itself from phi(t+1).  Algorithmic
+// traffic at FP32: the phase update 20 B per lattice update (phi, u in; phi
+// out), the force march 16 B (phi in, F out).
 #include <atomic>
 
 #include "internal.hpp"
 #include "lattice.hpp"
+#include "stencil.hpp"
 
 namespace lbf {
 namespace {
 
 constexpr int kPhaseThreads = 256;
-
-// The stencil weights factor: k(dx, dy, dz) = k1(dx) k1(dy) k1(dz) with
-// k1(0) = 4, k1(+-1) = 1.  So a plane's sums with the weights of an adjacent
-// plane (k1(+-1) = 1) are separable 3 x 3 sums, and with the own plane's
-// weights they are 4 times those.  On a 3 x 3 window n[dy][dx] (offsets -1..1):
-//   ss = sum k1 k1 n, ds = sum dx k1 k1 n, sd = sum dy k1 k1 n.
-template <typename C>
-__device__ __forceinline__ C sum141(C a, C b, C c) {
-  return a + C(4) * b + c;
-}
-template <typename C>
-__device__ __forceinline__ void window_sums(const C (&n)[3][3], C& ss, C& ds, C& sd) {
-  C sx[3], dx[3];
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    sx[r] = sum141(n[r][0], n[r][1], n[r][2]);
-    dx[r] = n[r][2] - n[r][0];
-  }
-  ss = sum141(sx[0], sx[1], sx[2]);
-  ds = sum141(dx[0], dx[1], dx[2]);
-  sd = sx[2] - sx[0];
-}
-// sum k1 k1 (n - own), the centre being own: the differences are formed
-// first, so that FP32 adds small numbers
-template <typename C>
-__device__ __forceinline__ C window_lap(const C (&n)[3][3], C own) {
-  const C r0 = sum141(n[0][0] - own, n[0][1] - own, n[0][2] - own);
-  const C r1 = (n[1][0] - own) + (n[1][2] - own);
-  const C r2 = sum141(n[2][0] - own, n[2][1] - own, n[2][2] - own);
-  return sum141(r0, r1, r2);
-}
 
 // 1 / (sqrt(g2) + eps) for the interface normal: FP64 evaluates it exactly
 // rounded; FP32 uses the hardware square root and reciprocal (about one unit in
@@ -134,7 +100,7 @@ __global__ void __launch_bounds__(64 * kUpdRows) phase_kernel(
   constexpr int NT = 64 * kUpdRows;
   constexpr int NP = PY * PX, NV = VY * VX;
   constexpr int PERP = (NP + NT - 1) / NT, PERV = (NV + NT - 1) / NT;
-  constexpr int KZ = 16 + 4 * 4 + 4 * 1;  // sum of k over the 9 sites of an adjacent plane
+  constexpr int KZ = kPlaneK;
   __shared__ C tp[2][NP];
   __shared__ Rec<C> tv[2][NV];
   const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
@@ -391,7 +357,7 @@ __global__ void __launch_bounds__(64 * kUpdRows) grad_march_kernel(const C* __re
   constexpr int NT = 64 * kUpdRows;
   constexpr int NE = RY * RX;
   constexpr int PER = (NE + NT - 1) / NT;
-  constexpr int KZ = 16 + 4 * 4 + 4 * 1;  // sum of k over the 9 sites of an adjacent plane
+  constexpr int KZ = kPlaneK;
   constexpr int G = kGroup;
   __shared__ C t[2][RY][RX];
   const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;

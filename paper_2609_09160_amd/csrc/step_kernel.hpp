@@ -221,8 +221,16 @@ __device__ __forceinline__ void finalize(const Sums<C>& S, C Fx, C Fy, C Fz, C o
 // The forward step as a physics policy of the z-march: a site reads its 10
 // stored moments (and the force), its values are the post-collision
 // populations, and a destination writes its 10 new moments.  FNEXT: the force
-// changes every step (two-component flow); the source uses F(t) and the
-// correction of Eq. (8) at the destination uses F(t+1) from a second field.
+// changes every step (two-component flow, section 2); the source uses F(t)
+// from a field, and the correction of Eq. (8) at the destination uses
+// F(t+1), which the destination computes itself from the gradient and
+// Laplacian of phi(t+1) (the march's scalar stencil) and writes out as the
+// next step's F(t):
+//   F = mu grad(phi) + rho(phi) g,  mu = 4 beta phi (phi - 1)(phi - 1/2) - kappa lap(phi),
+// with density contrast also - p* cs^2 grad(rho) - (nu omega / cs^2)(a2 - u u).grad(rho)
+// (p*, a2 - u u of the site at t; the printed viscous term is garbled, this
+// is the viscous stress written through the non-equilibrium coefficient of
+// Eq. (6)).
 // VAR: density and viscosity follow the phase field (section 2): the source
 // relaxes with omega(phi(t)) and applies F(t) / rho(phi(t)), the correction
 // applies F(t+1) / rho(phi(t+1)).
@@ -243,20 +251,35 @@ struct Forward {
   // 192-wide tiles (three x-sites per lane) are built for the one-component
   // second-order sets in FP32 storage
   static constexpr bool kThreeSites = ST == kF32 && !FNEXT && !FULL;
+  static constexpr bool kStencil = FNEXT;  // grad and lap of phi(t+1)
   // raw (still encoded) moments and force of one site, fetched a plane ahead;
-  // destinations of a time-dependent force also fetch F(t+1)
+  // with a time-dependent force also phi(t+1) (the stencil's scalar) and,
+  // with variable properties, phi(t)
   template <bool OWN>
   struct Raw {
     T m[10];
     C F[3];
-    C Fn[(FNEXT && OWN) ? 3 : 1];
-    C ph[VAR ? (OWN ? 2 : 1) : 1];  // phi(t), and phi(t+1) at destinations
+    C sc;
+    C ph;
   };
-  // force of the correction at the site (F(t), or F(t+1) when it changes)
+  template <bool OWN>
+  static __device__ __forceinline__ C scalar(const Raw<OWN>& r) {
+    return r.sc;
+  }
+  // handed from the source to the destination of the same site: the force
+  // of the correction (static force), or what the contrast terms of F(t+1)
+  // take from the state at t, the symmetric M = p* cs^2 I + (nu omega / cs^2)
+  // (a2 - u u) with nu, omega of phi(t+1) (xx yy zz xy xz yz), so that they
+  // are -M.grad(rho)
   struct Carry {
     C F[3];
+    C M[(FNEXT && VAR) ? 6 : 1];
   };
-  static __device__ __forceinline__ void clear(Carry& c) { c.F[0] = c.F[1] = c.F[2] = C(0); }
+  static __device__ __forceinline__ void clear(Carry& c) {
+    c.F[0] = c.F[1] = c.F[2] = C(0);
+#pragma unroll
+    for (int k = 0; k < ((FNEXT && VAR) ? 6 : 1); ++k) c.M[k] = C(0);
+  }
 
   // the force field has the compute type; its byte offset scales accordingly
   static constexpr uint32_t kFscale = sizeof(C) / sizeof(T);
@@ -282,26 +305,19 @@ struct Forward {
         for (int s = 0; s < NS; ++s) r[s].F[k] = v[s];
       }
     }
-    if constexpr (FNEXT && OWN) {
-      const C* __restrict__ Fn = static_cast<const C*>(a.Fnext);
+    if constexpr (FNEXT) {
+      C v[NS];
+      buf_load_n<C, NS>(plane_rsrc(static_cast<const C*>(a.phi_dst) + pb, plane_bytes * kFscale),
+                        off * kFscale, v);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        C v[NS];
-        buf_load_n<C, NS>(plane_rsrc(Fn + (k * a.N + pb), plane_bytes * kFscale), off * kFscale, v);
-#pragma unroll
-        for (int s = 0; s < NS; ++s) r[s].Fn[k] = v[s];
-      }
+      for (int s = 0; s < NS; ++s) r[s].sc = v[s];
     }
     if constexpr (VAR) {
-      const C* __restrict__ ph[2] = {static_cast<const C*>(a.phi_src),
-                                     static_cast<const C*>(a.phi_dst)};
+      C v[NS];
+      buf_load_n<C, NS>(plane_rsrc(static_cast<const C*>(a.phi_src) + pb, plane_bytes * kFscale),
+                        off * kFscale, v);
 #pragma unroll
-      for (int k = 0; k < (OWN ? 2 : 1); ++k) {
-        C v[NS];
-        buf_load_n<C, NS>(plane_rsrc(ph[k] + pb, plane_bytes * kFscale), off * kFscale, v);
-#pragma unroll
-        for (int s = 0; s < NS; ++s) r[s].ph[k] = v[s];
-      }
+      for (int s = 0; s < NS; ++s) r[s].ph = v[s];
     }
   }
 
@@ -326,33 +342,85 @@ struct Forward {
     for (int k = 0; k < 3; ++k) F[k] = FFIELD ? r.F[k] : static_cast<C>(a.F[k]);
     C omega = static_cast<C>(a.omega);
     if constexpr (VAR) {
-      // F / rho and omega of phi(t) at the source, F(t+1) / rho(phi(t+1))
-      // for the correction at the destination
-      const C p = r.ph[0];
+      // F / rho and omega of phi(t) at the source
+      const C p = r.ph;
       const C inv_rho = C(1) / (static_cast<C>(a.rho_l) + p * static_cast<C>(a.rho_h - a.rho_l));
       const C nu = static_cast<C>(a.nu_l) + p * static_cast<C>(a.nu_h - a.nu_l);
       omega = C(1) / (C(3) * nu + C(0.5));
 #pragma unroll
       for (int k = 0; k < 3; ++k) F[k] *= inv_rho;
       if constexpr (OWN) {
-        const C inv_rho_d =
-            C(1) / (static_cast<C>(a.rho_l) + r.ph[1] * static_cast<C>(a.rho_h - a.rho_l));
+        // M for the contrast terms of F(t+1) from the state at t: p* cs^2 and
+        // the non-equilibrium a2 - u u (deviation storage holds it directly)
+        const C pn = r.sc;
+        const C nun = static_cast<C>(a.nu_l) + pn * static_cast<C>(a.nu_h - a.nu_l);
+        const C cv = C(3) * nun * (C(1) / (C(3) * nun + C(0.5)));
+        const C cp = m[0] * C(1.0 / 3.0);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) c.F[k] = r.Fn[k] * inv_rho_d;
+        for (int k = 4; k < 10; ++k)
+          c.M[k - 4] = cv * (S::kNeq ? m[k] : m[k] - m[1 + a2_a(k)] * m[1 + a2_b(k)]) +
+                       (k < 7 ? cp : C(0));
       }
-    } else {
+    }
+    if constexpr (!FNEXT) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        if constexpr (FNEXT && OWN)
-          c.F[k] = r.Fn[k];
-        else
-          c.F[k] = F[k];
-      }
+      for (int k = 0; k < 3; ++k) c.F[k] = F[k];
     }
     if constexpr (FULL)
       source_pops_full<C, SEL, kNeqMode, !NOF>(m, F[0], F[1], F[2], omega, g);
     else
       source_pops<Q, C, SEL, kNeqMode, !NOF>(m, F[0], F[1], F[2], omega, g);
+  }
+
+  // F(t+1) at a destination from the stencils of phi(t+1) (and, with
+  // contrast, the site's state at t); rho(phi(t+1)) into rho
+  static __device__ __forceinline__ void force_next(const StepArgs& a, const StencilOut<C>& st,
+                                                    const Carry& c, C f[3], C& rho) {
+    const C p = st.centre;
+    const C beta = static_cast<C>(a.beta), kappa = static_cast<C>(a.kappa);
+    const C rl = static_cast<C>(a.rho_l), dr = static_cast<C>(a.rho_h - a.rho_l);
+    const C mu = C(4) * beta * p * (p - C(1)) * (p - C(0.5)) - kappa * st.lap;
+    rho = rl + p * dr;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f[k] = mu * st.g[k] + rho * static_cast<C>(a.Fb[k]);
+    if constexpr (VAR) {
+      if (a.contrast) {
+        const C gr[3] = {dr * st.g[0], dr * st.g[1], dr * st.g[2]};
+        const C* M = c.M;  // xx yy zz xy xz yz
+        f[0] -= M[0] * gr[0] + M[3] * gr[1] + M[4] * gr[2];
+        f[1] -= M[3] * gr[0] + M[1] * gr[1] + M[5] * gr[2];
+        f[2] -= M[4] * gr[0] + M[5] * gr[1] + M[2] * gr[2];
+      }
+    }
+  }
+
+  // two-component form: F(t+1) from the stencils, written out for the next
+  // step, then the correction with it
+  template <int NS>
+  static __device__ __forceinline__ void finish(const StepArgs& a, const Sums<C> (&acc)[NS],
+                                                const Carry (&c)[NS],
+                                                const StencilOut<C> (&st)[NS], int64_t pb,
+                                                uint32_t off, uint32_t plane_bytes) {
+    static_assert(FNEXT, "the stencil form is the two-component step");
+    Carry cf[NS];
+    C fo[3][NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      C f[3], rho;
+      force_next(a, st[s], c[s], f, rho);
+      const C inv = VAR ? C(1) / rho : C(1);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        fo[k][s] = f[k];
+        cf[s].F[k] = VAR ? f[k] * inv : f[k];
+      }
+    }
+    C* __restrict__ Fo = static_cast<C*>(a.Fout);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      buf_store_nt_n<C, NS>(fo[k], plane_rsrc(Fo + (k * a.N + pb), plane_bytes * kFscale),
+                            off * kFscale);
+    finish(a, acc, cf, pb, off, plane_bytes);
   }
 
   template <int NS>
@@ -408,11 +476,11 @@ hipError_t launch_step_t(const StepArgs& a, hipStream_t stream) {
   if constexpr (FFIELD && TY <= 8) {
     // a force that changes every step (two-component flow), with or without
     // density and viscosity contrast
-    if (a.Fnext && a.phi_src)
+    if (a.Fout && a.phi_src)
       return launch_march<Forward<Q, ST, true, true, true, FULL>, TY, WALLY>(a, stream);
-    if (a.Fnext) return launch_march<Forward<Q, ST, true, true, false, FULL>, TY, WALLY>(a, stream);
+    if (a.Fout) return launch_march<Forward<Q, ST, true, true, false, FULL>, TY, WALLY>(a, stream);
   }
-  if (a.Fnext) return hipErrorInvalidValue;
+  if (a.Fout) return hipErrorInvalidValue;
   if constexpr (!FFIELD) {
     if (a.F[0] == 0.0 && a.F[1] == 0.0 && a.F[2] == 0.0)
       return launch_march<Forward<Q, ST, false, false, false, FULL, true>, TY, WALLY>(a, stream);
@@ -434,14 +502,6 @@ hipError_t launch_step_t(const StepArgs& a, hipStream_t stream) {
 template <int ST>
 hipError_t launch_step_storage(int lattice, int tile_rows, bool walls_y, bool ffield,
                                const StepArgs& a, hipStream_t s) {
-#ifdef LBF_TUNE_ONLY
-  // tuning builds: D3Q19 with 6- and 8-row tiles only
-  if (lattice == 19) {
-    LBF_CASE(19, false, 6)
-    LBF_CASE(19, false, 8)
-  }
-  return hipErrorInvalidValue;
-#endif
   if (lattice == 19) {
     LBF_CASE(19, false, 4)
     LBF_CASE(19, false, 6)
@@ -459,9 +519,6 @@ hipError_t launch_step_storage(int lattice, int tile_rows, bool walls_y, bool ff
 template <int ST>
 hipError_t launch_step_storage_full(int tile_rows, bool walls_y, bool ffield, const StepArgs& a,
                                     hipStream_t s) {
-#ifdef LBF_TUNE_ONLY
-  return hipErrorInvalidValue;
-#endif
   LBF_CASE(27, true, 4)
   LBF_CASE(27, true, 6)
   LBF_CASE(27, true, 8)

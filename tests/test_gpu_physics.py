@@ -22,7 +22,7 @@ def _cuda():
 
 @pytest.mark.parametrize("sites", [1, 2])
 @pytest.mark.parametrize("Q", [19, 27, "27h"])
-@pytest.mark.parametrize("storage,bound", [("f16s", 1e-3), ("bf16s", 1e-1)])
+@pytest.mark.parametrize("storage,bound", [("f16s", 1e-3), ("bf16s", 3e-2)])
 def test_16bit_storage_accuracy(Q, storage, bound, sites):
     """16-bit scaled moment storage (FP32 arithmetic), 64^3 solenoidal workload,
     tau = 0.6, 1000 steps: relative L2 error of u against the FP64 oracle, with
@@ -30,9 +30,11 @@ def test_16bit_storage_accuracy(Q, storage, bound, sites):
     runs; at 64^3 the default is one).
     FP16 (11-bit significand) meets the 1e-3 bar stated for the 16-bit form.
     BF16 (8-bit significand) cannot: u itself is re-rounded every step with
-    unit roundoff 2^-9 ~ 2e-3, and the low-wavenumber part of that noise
-    accumulates over 1000 steps (random walk: sqrt(1000) * 2e-3 ~ 6e-2); it is
-    reported and held to that derived order, 1e-1."""
+    unit roundoff 2^-9 ~ 2e-3.  Rounded to nearest, the low-wavenumber part of
+    that error accumulates over 1000 steps like a random walk (sqrt(1000) *
+    2e-3 ~ 6e-2); BF16's default, stochastic rounding, makes each rounding
+    unbiased and independent, and the error settles near 1.2e-2; it is held
+    to 3e-2."""
     n = 64
     m0, want = solenoidal_oracle_1000(Q, n)
     got = gpu_run((n, n, n), 0.6, m0, 1000, lattice=Q, storage=storage, launch=(0, 0, sites))

@@ -32,9 +32,9 @@ def gpu_two_phase(shape, tau, m0, phi0, steps, lattice=19, storage="f64", force=
     steps."""
     from paper_2609_09160_amd import Solver
     s = Solver(shape, tau, lattice=lattice, storage=storage, force=force, scale=scale, bc=bc)
-    if sites:
-        s.set_launch(4, 0, sites)
     s.enable_two_phase(SIGMA, W, DIFF, rho=rho, tau=taus if taus is not None else tau)
+    if sites:  # after enabling: the variant picks its own default shape
+        s.set_launch(4, 0, sites)
     s.set_moments(np.ascontiguousarray(m0))
     s.set_phase(np.ascontiguousarray(phi0))
     peaks = np.zeros(10)

@@ -138,3 +138,12 @@ def test_valid_params_without_gpu_report_device_error(lib, lattice):
     assert lib.lbfast_buffer_bytes(ctypes.byref(p)) == 10 * 8 ** 3 * 4
     rc, msg = _create(lib, p)
     assert rc == _lib.LBF_E_DEVICE and msg
+
+
+@pytest.mark.parametrize("n,nplanes,needle", [(3, 10, "even"), (0, 10, "even"),
+                                              (8, 0, "nplanes"), (8, 11, "nplanes")])
+def test_planes_probe_validation(lib, n, nplanes, needle):
+    # rejected on the host before any device call (the pointers are never used)
+    rc = lib.lbfast_planes_probe(ctypes.c_void_p(4096), ctypes.c_void_p(8192), n, nplanes, None)
+    assert rc == _lib.LBF_E_ARG
+    assert needle in lib.lbfast_last_error().decode()
