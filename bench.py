@@ -500,6 +500,8 @@ def main():
     ap.add_argument("--z-chunk", type=int, default=0, help="launch override (0 = default)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the library's stream copy (counter calibration)")
+    ap.add_argument("--two-phase-only", action="store_true",
+                    help="time only the two-component droplet workload (for counter passes)")
     ap.add_argument("--copy-ceilings", action="store_true",
                     help="only time copies of the step's volume by three routes")
     args = ap.parse_args()
@@ -519,6 +521,12 @@ def main():
 
     if args.copy_ceilings:
         print(json.dumps(copy_ceilings()), flush=True)
+        return
+
+    if args.two_phase_only:
+        print(json.dumps({"two_phase": run_two_phase(steps=args.steps, warmup=args.warmup),
+                          "two_phase_contrast": run_two_phase(steps=args.steps, warmup=args.warmup,
+                                                              contrast=True)}), flush=True)
         return
 
     if args.copy_probe:

@@ -38,6 +38,10 @@ struct StepArgs {
   double F[3];         // uniform force (used when Ffield == nullptr)
   float scale[10];     // 16-bit storage: value = scale * q
   float inv_scale[10];
+  // 16-bit storage: inv_scale[k] / D (D the velocity set's weight
+  // denominator) for p* and u as a hi + lo pair, hi = fl(1/D) inv_scale[k],
+  // lo = fl(1/D - fl(1/D)) inv_scale[k] (exact: the scales are powers of two)
+  float enc_hi[4], enc_lo[4];
   uint32_t sr_seed;    // 16-bit storage: seed of this step's stochastic rounding
   int stochastic;      // 16-bit storage: round p* and u stochastically
   // adjoint step only (src/dst then hold the adjoint variables at t+1 / t)

@@ -132,6 +132,18 @@ __device__ __forceinline__ V buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   }
 }
 
+// one value with the default cache policy (data read again soon)
+template <typename V>
+__device__ __forceinline__ void buf_store(V v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (sizeof(V) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+  } else {
+    static_assert(sizeof(V) == 8, "4 or 8 bytes");
+    using U2 = unsigned int __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, off, 0, 0);
+  }
+}
+
 template <typename V>
 __device__ __forceinline__ void buf_store_nt(V v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
   if constexpr (sizeof(V) == 2) {
@@ -316,6 +328,11 @@ struct Storage<kF16S> {
   static __device__ __forceinline__ T encode_sr(C v, float inv_s, uint32_t r) {
     return f32_to_f16_bits(round_stochastic<13>(v * inv_s, r));
   }
+  // the same for a value already in storage units
+  static __device__ __forceinline__ T encode_unit(C v) { return f32_to_f16_bits(v); }
+  static __device__ __forceinline__ T encode_unit_sr(C v, uint32_t r) {
+    return f32_to_f16_bits(round_stochastic<13>(v, r));
+  }
   static __device__ __forceinline__ void store(T* p, int64_t i, C v, float inv_s) {
     __builtin_nontemporal_store(f32_to_f16_bits(v * inv_s), p + i);
   }
@@ -337,6 +354,10 @@ struct Storage<kBF16S> {
   // stochastic rounding to bfloat16 (the upper half of binary32)
   static __device__ __forceinline__ T encode_sr(C v, float inv_s, uint32_t r) {
     return static_cast<T>(__float_as_uint(round_stochastic<16>(v * inv_s, r)) >> 16);
+  }
+  static __device__ __forceinline__ T encode_unit(C v) { return f32_to_bf16_bits(v); }
+  static __device__ __forceinline__ T encode_unit_sr(C v, uint32_t r) {
+    return static_cast<T>(__float_as_uint(round_stochastic<16>(v, r)) >> 16);
   }
   static __device__ __forceinline__ void store(T* p, int64_t i, C v, float inv_s) {
     __builtin_nontemporal_store(f32_to_bf16_bits(v * inv_s), p + i);

@@ -277,6 +277,15 @@ int step_args(const lbfast_ctx* h, lbf::StepArgs* a) {
     a->scale[k] = h->scale[k];
     a->inv_scale[k] = h->inv_scale[k];
   }
+  {
+    const double inv_d = 1.0 / ((h->p.lattice == LBF_D3Q19) ? 9.0 : 27.0);
+    const float hi = static_cast<float>(inv_d);
+    const float lo = static_cast<float>(inv_d - static_cast<double>(hi));
+    for (int k = 0; k < 4; ++k) {
+      a->enc_hi[k] = hi * h->inv_scale[k];
+      a->enc_lo[k] = lo * h->inv_scale[k];
+    }
+  }
   a->Ffield = h->Ffield;
   a->stochastic = h->p.rounding == LBF_ROUND_STOCHASTIC ||
                   (h->p.rounding == LBF_ROUND_AUTO && h->p.storage == LBF_BF16S);

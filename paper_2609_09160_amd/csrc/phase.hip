@@ -112,10 +112,14 @@ __global__ void __launch_bounds__(64 * kUpdRows) phase_kernel(
   const int x0 = tx * 64, y0 = ty * kUpdRows;
   const int z0 = zc * zchunk, z1 = min(z0 + zchunk, nz);
   const int64_t plane = static_cast<int64_t>(nx) * ny;
+  // Loads go through buffer resources of one plane with 32-bit in-plane byte
+  // offsets (the host keeps a plane of doubles below 4 GiB).
   // staged phi values: in-plane offset (a wall's ghost rows hold the clamped
   // row, which is the mirror image one site beyond the wall; rows further out
   // feed only slots that are never read for an owned site)
-  int64_t poff[PERP];
+  const uint32_t pbytes_c = static_cast<uint32_t>(plane * sizeof(C));
+  const uint32_t pbytes_t = static_cast<uint32_t>(plane * sizeof(typename S::T));
+  uint32_t poff[PERP];
   bool pact[PERP];
 #pragma unroll
   for (int k = 0; k < PERP; ++k) {
@@ -124,13 +128,13 @@ __global__ void __launch_bounds__(64 * kUpdRows) phase_kernel(
     const int ry = pact[k] ? e / PX : 0, rx = pact[k] ? e - ry * PX : 0;
     const int yr = y0 + ry - 2;
     const int yw = walls_y ? clampi(yr, 0, ny - 1) : pmod(yr, ny);
-    poff[k] = pact[k] ? static_cast<int64_t>(yw) * nx + pmod(x0 + rx - 2, nx) : 0;
+    poff[k] = pact[k] ? static_cast<uint32_t>((yw * nx + pmod(x0 + rx - 2, nx)) * sizeof(C)) : 0u;
   }
   // record slots: the source site (the mirror site for a ghost), the top-left
   // of its 3 x 3 phi window in the staged plane, and whether v_y is reversed.
   // Rows: the source row ys lies in [y0 - 1, y0 + kUpdRows], so the window
   // rows ys - y0 + 1 .. ys - y0 + 3 lie in [0, PY).
-  int64_t voff[PERV];
+  uint32_t voff[PERV];
   int vwin[PERV];
   bool vact[PERV], vneg[PERV];
 #pragma unroll
@@ -142,7 +146,9 @@ __global__ void __launch_bounds__(64 * kUpdRows) phase_kernel(
     const int ys = walls_y ? clampi(yr, 0, ny - 1) : pmod(yr, ny);
     vneg[k] = walls_y && ys != yr;
     vwin[k] = (walls_y ? ys - y0 + 1 : ry) * PX + rx;
-    voff[k] = vact[k] ? static_cast<int64_t>(ys) * nx + pmod(x0 + rx - 1, nx) : 0;
+    voff[k] = vact[k] ? static_cast<uint32_t>((ys * nx + pmod(x0 + rx - 1, nx)) *
+                                              sizeof(typename S::T))
+                      : 0u;
   }
   // register banks: slot i of a group starting at plane qs holds phi of
   // plane qs + i and u of plane qs + i - 1 (for V(qs + i - 1))
@@ -155,13 +161,13 @@ __global__ void __launch_bounds__(64 * kUpdRows) phase_kernel(
       constexpr int i = decltype(I)::value;
       const int64_t zp = static_cast<int64_t>(pmod(min(qs + i, z1 + 1), nz)) * plane;
 #pragma unroll
-      for (int k = 0; k < PERP; ++k) rp[b][i][k] = phi[zp + poff[k]];
+      for (int k = 0; k < PERP; ++k) rp[b][i][k] = buf_load<C>(plane_rsrc(phi + zp, pbytes_c), poff[k]);
       const int64_t zu = static_cast<int64_t>(pmod(clampi(qs + i - 1, z0 - 1, z1), nz)) * plane;
 #pragma unroll
       for (int k = 0; k < PERV; ++k) {
-        ux[b][i][k] = S::load(st + N, zu + voff[k], s1);
-        uy[b][i][k] = S::load(st + 2 * N, zu + voff[k], s2);
-        uz[b][i][k] = S::load(st + 3 * N, zu + voff[k], s3);
+        ux[b][i][k] = S::decode(buf_load<typename S::T>(plane_rsrc(st + N + zu, pbytes_t), voff[k]), s1);
+        uy[b][i][k] = S::decode(buf_load<typename S::T>(plane_rsrc(st + 2 * N + zu, pbytes_t), voff[k]), s2);
+        uz[b][i][k] = S::decode(buf_load<typename S::T>(plane_rsrc(st + 3 * N + zu, pbytes_t), voff[k]), s3);
       }
     });
   };
@@ -176,6 +182,7 @@ __global__ void __launch_bounds__(64 * kUpdRows) phase_kernel(
   }
   const int x = x0 + lane, y = y0 + wy;
   const bool mine = x < nx && y < ny;
+  const uint32_t own_off = mine ? static_cast<uint32_t>((y * nx + x) * sizeof(C)) : 0u;
   // divergence and Laplacian sums of phi'(q - 3) (m) and phi'(q - 2) (0), the
   // Laplacian of the latter relative to ref0
   C dvm = 0, lm = 0, pm = 0;
@@ -260,8 +267,8 @@ __global__ void __launch_bounds__(64 * kUpdRows) phase_kernel(
       const C ld = lu + C(KZ) * (own - pm), lc = C(4) * lu;
       const int d = q - 3;
       if (mine && d >= z0 && d < z1)
-        out[static_cast<int64_t>(d) * plane + static_cast<int64_t>(y) * nx + x] =
-            pm - div_by<72>(dvm + dvd) + D * div_by<36>(lm + ld);
+        buf_store<C>(pm - div_by<72>(dvm + dvd) + D * div_by<36>(lm + ld),
+                     plane_rsrc(out + static_cast<int64_t>(d) * plane, pbytes_c), own_off);
       dvm = dv0 + dvc;
       lm = l0 - C(KZ) * (own - ref0) + lc;
       pm = own;

@@ -440,15 +440,28 @@ struct Forward {
         // drops every change below half a unit in the last place and a slowly
         // evolving flow stalls.  a2 - u u, relaxed at every step, rounds to
         // nearest, with the velocity as it will be read back.
+        // Without a force, p* and u are the sums times 1/D: they go to
+        // storage units in one step, the sum times (inv_scale / D) as a hi +
+        // lo pair, which rounds exactly as dividing first and scaling after
+        // (the scales are powers of two) with one multiplication less.
+        C un[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if constexpr (NOF) {
+            const C t = k == 0 ? acc[s].s0 : (k == 1 ? acc[s].jx : (k == 2 ? acc[s].jy : acc[s].jz));
+            un[k] = __builtin_fmaf(t, a.enc_hi[k], t * a.enc_lo[k]);
+          } else {
+            un[k] = out[s][k] * a.inv_scale[k];
+          }
+        }
         if (a.stochastic) {
           const uint32_t site = static_cast<uint32_t>(pb) + off / sizeof(T) + s;
           const uint32_t h = hash32(site ^ a.sr_seed);
 #pragma unroll
-          for (int k = 0; k < 4; ++k)
-            q[s][k] = S::encode_sr(out[s][k], a.inv_scale[k], (h >> (8 * k)) & 0xffu);
+          for (int k = 0; k < 4; ++k) q[s][k] = S::encode_unit_sr(un[k], (h >> (8 * k)) & 0xffu);
         } else {
 #pragma unroll
-          for (int k = 0; k < 4; ++k) q[s][k] = S::encode(out[s][k], a.inv_scale[k]);
+          for (int k = 0; k < 4; ++k) q[s][k] = S::encode_unit(un[k]);
         }
         C ur[3];
 #pragma unroll
