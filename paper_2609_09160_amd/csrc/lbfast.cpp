@@ -149,13 +149,6 @@ namespace {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Block order of the adjoint step: contiguous tile ranges per XCD (1) or the
-// hardware order (0); the forward step uses the hardware order, measured
-// as fast for FP32 and faster for 16-bit storage at 512^3.
-#ifndef LBF_ADJOINT_XCD_REMAP
-#define LBF_ADJOINT_XCD_REMAP 1
-#endif
-
 // LDS of one step workgroup: staged populations x (rows + 2) x (64 S + 2)
 // columns, plus the x-halo column buffer
 // LDS of one step workgroup; the two-component step stages phi(t+1) in one
@@ -287,6 +280,13 @@ int step_args(const lbfast_ctx* h, lbf::StepArgs* a) {
     }
   }
   a->Ffield = h->Ffield;
+  // Block order, measured at 512^3 on one box with the two orders built as
+  // separate libraries and run interleaved: contiguous tile ranges per XCD
+  // are faster for FP64 (21% for D3Q19, 6% for D3Q27h) and for FP32 D3Q27
+  // (3%), the hardware order for 16-bit storage (2-5%); D3Q19 FP32 and its
+  // adjoint are equal within 1% and keep the hardware order.
+  a->xcd_remap = h->p.storage == LBF_F64 ||
+                 (h->p.storage == LBF_F32 && h->p.lattice != LBF_D3Q19);
   a->stochastic = h->p.rounding == LBF_ROUND_STOCHASTIC ||
                   (h->p.rounding == LBF_ROUND_AUTO && h->p.storage == LBF_BF16S);
   if (h->two_phase) {
@@ -986,7 +986,6 @@ int lbfast_adjoint(lbfast_t h, int64_t nsteps, int64_t every, const void* ckpt_d
   // site per lane and 8-row tiles (FP64: 6); lbfast_set_adjoint_launch may
   // choose two or three sites per lane with 4- or 6-row tiles (FP32)
   aa.lane_sites = h->adj_sites ? h->adj_sites : 1;
-  aa.xcd_remap = LBF_ADJOINT_XCD_REMAP;
   const int adj_rows = h->adj_rows ? h->adj_rows : ((h->p.storage == LBF_F64) ? 6 : 8);
   if (int rc = resolve_zchunk(h, aa.lane_sites, adj_rows, &aa.tiles_x, &aa.tiles_y, &aa.zchunks,
                               &aa.zchunk))

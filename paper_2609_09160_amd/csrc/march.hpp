@@ -46,8 +46,8 @@
 //     input is read from HBM once per update (plus L2-resident halos) and each
 //     output written once, with no population array anywhere;
 //   * block ids can be remapped so that each XCD (own L2) gets a contiguous
-//     range of tiles, y-neighbours first (a.xcd_remap); measured at 512^3 the
-//     plain order is as fast for FP32 and faster for 16-bit storage.
+//     range of tiles, y-neighbours first (a.xcd_remap); the host chooses the
+//     order per storage form, from measurement.
 #pragma once
 
 #ifndef LBF_PREFETCH_DEPTH
