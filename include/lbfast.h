@@ -224,9 +224,13 @@ int lbfast_set_launch(lbfast_t h, int tile_rows, int z_chunk);
  * 2-wide load or store per moment plane; needs an even nx and tiles of at
  * most 8 rows) or 3 (192-wide tiles, 3-wide accesses; F32 storage, LBF_D3Q19
  * or LBF_D3Q27, one component, nx divisible by 3, tiles of at most 8 rows;
- * enabling the two-component variant returns to one site per lane).  The default is 2 where nx is even and at least 128 and the
- * 128-wide tiles leave no more of the last tile empty than 64-wide ones (1
- * for LBF_D3Q27H with F64 storage, where two sites spill registers).  If the
+ * enabling the two-component variant returns to one site per lane, as it
+ * does from two with variable density or viscosity).  The default is 2 where
+ * nx is even and at least 128 and the 128-wide tiles leave no more of the
+ * last tile empty than 64-wide ones, else 3 where nx is divisible by 3 and
+ * at least 192 and 192-wide tiles leave no more empty (F32, LBF_D3Q19 or
+ * LBF_D3Q27), else 1; always 1 for LBF_D3Q27H with F64 or F16S storage,
+ * where two sites spill registers.  If the
  * current tile height does not fit the 160 KiB of LDS with the new setting,
  * the tallest of 8, 6 and 4 rows that does is taken.  Same formulas per site;
  * results may differ between settings in the last bits. */
@@ -246,10 +250,11 @@ int lbfast_set_lane_sites(lbfast_t h, int sites);
  * same as a force per unit volume where rho = 1); the last two terms vanish
  * at equal densities.  Walls: y only, with mirror images for the phase-field
  * stencils.  No per-site force field in this mode.  Each lbfast_step then
- * performs, in order: phi(t+1) from phi(t) and u(t); F(t+1) from phi(t+1)
- * (its pressure and viscous terms from p*, u, a2 at t); the fused step with
+ * performs, in order: phi(t+1) from phi(t) and u(t); the fused step with
  * F(t)/rho(t) and omega(t) at the sources and F(t+1)/rho(t+1) in the
- * correction of Eq. (8).  FTCS is stable for diffusivity < ~0.34 with these
+ * correction of Eq. (8), where each destination computes F(t+1) itself from
+ * phi(t+1) (its pressure and viscous terms from p*, u, a2 of the site at t)
+ * and keeps it as the next step's F(t).  FTCS is stable for diffusivity < ~0.34 with these
  * stencils (not checked). */
 typedef struct lbfast_phase_params {
   uint32_t struct_size; /* = sizeof(lbfast_phase_params) */

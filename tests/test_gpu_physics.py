@@ -7,7 +7,7 @@ import pytest
 
 from paper_2609_09160_amd import inputs
 
-from gpu_util import (gpu_run, lattice_number, oracle_run, oracle_site_update, say,
+from gpu_util import (GROUPS, gpu_run, lattice_number, oracle_run, oracle_site_update, say,
                       solenoidal_oracle_1000, u_rel_l2)
 
 pytestmark = pytest.mark.gpu
@@ -91,6 +91,53 @@ def test_storage_forms_512_vs_fp64(Q):
         say(f"512^3 Q{Q} {storage} ({rounding}): u rel L2 vs FP64 after {steps} steps = {e:.3e}")
         assert e <= bar
     del ref, m0
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("storage,bound", [("f16s", 2e-3), ("bf16s", 1.6e-2)])
+@pytest.mark.parametrize("Q", [19, 27, "27h"])
+def test_sampled_sites_512_16bit(Q, storage, bound):
+    """Full size, bench launch configuration, 16-bit storage with its default
+    rounding (FP16 to nearest, BF16 stochastic): one step of the 512^3
+    workload; 48 sampled sites against the oracle's single-site update from
+    the stored (decoded) neighbourhood.  The difference is the rounding of the
+    output to the storage format, less than one unit in the last place of the
+    value: 2^-10 of it for FP16 (half that, rounded to nearest) and 2^-7 for
+    BF16, so at most that fraction of the group's magnitude; the bounds are
+    twice that."""
+    import torch
+    from paper_2609_09160_amd import Solver
+    n, tau = 512, 0.6
+    m32 = inputs.solenoidal_field((n, n, n), device="cuda").float()
+    s = Solver((n, n, n), tau, lattice=Q, storage=storage)
+    s.set_moments(m32)
+    del m32
+    torch.cuda.empty_cache()
+    start = s.moments(dtype=torch.float32)
+    s.step(1)
+    out = s.moments(dtype=torch.float32)
+    s.close()
+    rng = np.random.Generator(np.random.PCG64(1512 + lattice_number(Q)))
+    pts = [(0, 0, 0), (511, 511, 511), (127, 7, 0), (128, 8, 511), (255, 255, 256), (0, 511, 1)]
+    pts += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(42)]
+    got_all, want_all = [], []
+    for (x, y, z) in pts:
+        ix = torch.tensor([(x - 1) % n, x, (x + 1) % n], device="cuda")
+        iy = torch.tensor([(y - 1) % n, y, (y + 1) % n], device="cuda")
+        iz = torch.tensor([(z - 1) % n, z, (z + 1) % n], device="cuda")
+        crop = start[:, iz][:, :, iy][:, :, :, ix].double().cpu().numpy()
+        want_all.append(oracle_site_update(crop, Q, tau))
+        got_all.append(out[:, z, y, x].double().cpu().numpy())
+    got, want = np.stack(got_all, axis=1), np.stack(want_all, axis=1)
+    # judged per group (p*, u, a2) against the group's magnitude in the whole
+    # output, the scale its storage rounding acts on
+    err = 0.0
+    for lo, hi in GROUPS:
+        ref = float(out[lo:hi].abs().max())
+        err = max(err, float(np.abs(got[lo:hi] - want[lo:hi]).max()) / ref)
+    say(f"Q{Q} {storage}: max error over sampled sites, relative to the group magnitude: {err:.3e}")
+    assert err <= bound
+    del out, start
     torch.cuda.empty_cache()
 
 
