@@ -62,7 +62,9 @@ struct alignas(4 * sizeof(C)) Rec {
 // its phi_0.  They are summed relative to the thread's own phi of plane p and
 // corrected, once phi_0 is known, by the weight sum (36) times the
 // difference, so FP32 adds only small differences.
-constexpr int kUpdRows = 8;
+// 16 rows: the record ring and the phi halo are a smaller share of the tile
+// than with 8 (measured 1% faster for the whole two-component step at 256^3)
+constexpr int kUpdRows = 16;
 // Loads ahead of use in the staged marches.  Iterations run in groups of
 // kGroup planes, with two register banks: at the start of a group the next
 // group's values are issued into one bank, and the current group is taken
