@@ -79,8 +79,15 @@ enum { LBF_D3Q19 = 19, LBF_D3Q27 = 27, LBF_D3Q27H = 270 };
  * storage the second-order planes hold the deviation a2 - u u (u as stored),
  * p* and u are deviations already; the ABI always exchanges the total a2.
  * lbfast_set_moments rounds to nearest even; the step rounds as
- * lbfast_params.rounding says. */
-enum { LBF_F64 = 0, LBF_F32 = 1, LBF_F16S = 2, LBF_BF16S = 3 };
+ * lbfast_params.rounding says.
+ * F16SU = F16S with each velocity component split over two binary16 words,
+ * u = s_u (hi + 2^-11 lo), hi the rounding of u/s_u and lo that of the
+ * remainder (both to nearest even): 22 significant bits for u, which carries
+ * almost all of the 16-bit storage error of a slowly evolving flow.  A state
+ * buffer then holds 13 planes of N binary16 words: the ten moment planes
+ * (planes 1..3 the hi words), then the lo words of u_x, u_y, u_z.  LBF_D3Q19
+ * and LBF_D3Q27 only, one component, rounding to nearest only. */
+enum { LBF_F64 = 0, LBF_F32 = 1, LBF_F16S = 2, LBF_BF16S = 3, LBF_F16SU = 4 };
 
 /* boundary per axis: periodic, or stationary halfway bounce-back walls at
  * both ends (walls at -1/2 and n-1/2; every layer is fluid).  Walls are
@@ -90,7 +97,7 @@ enum { LBF_PERIODIC = 0, LBF_WALLS = 1 };
 typedef struct lbfast_params {
   uint32_t struct_size; /* = sizeof(lbfast_params) */
   int32_t lattice;      /* LBF_D3Q19, LBF_D3Q27 or LBF_D3Q27H */
-  int32_t storage;      /* LBF_F64, LBF_F32, LBF_F16S, LBF_BF16S */
+  int32_t storage;      /* LBF_F64, LBF_F32, LBF_F16S, LBF_BF16S, LBF_F16SU */
   int32_t bc[3];        /* per axis x, y, z: LBF_PERIODIC or LBF_WALLS */
   int64_t nx, ny, nz;   /* grid, each >= 1 (>= 2 on a walled axis) */
   double tau;           /* relaxation time, > 1/2 */
@@ -183,10 +190,11 @@ int lbfast_reduce(lbfast_t h, double out[5]);
  * capture, tight serving loops, harnesses that forbid hipMalloc): the sums of
  * lbfast_reduce over any moment array, with no handle and no allocation.
  *   state_dev  10 x n_sites values in the storage format `storage`
- *              (LBF_F64, LBF_F32, LBF_F16S or LBF_BF16S), device memory, e.g.
- *              lbfast_state_ptr() or a checkpoint slot; read only;
+ *              (LBF_F64, LBF_F32, LBF_F16S, LBF_BF16S; 13 x n_sites for
+ *              LBF_F16SU), device memory, e.g. lbfast_state_ptr() or a
+ *              checkpoint slot; read only;
  *   scale      the ten 16-bit storage scales (lbfast_get_scales), host array;
- *              required for F16S/BF16S, ignored (may be NULL) otherwise;
+ *              required for 16-bit storage, ignored (may be NULL) otherwise;
  *   out_dev    5 doubles of device memory, receives
  *              [sum a0, sum a1x, sum a1y, sum a1z, 1/2 sum |a1|^2];
  *   stream     hipStream_t of the current device (NULL = legacy stream).

@@ -16,13 +16,14 @@ HEADERS = (HEADER, os.path.join(os.path.dirname(_HERE), "include", "lbfast_measu
 LBF_OK, LBF_E_ARG, LBF_E_UNSUPPORTED, LBF_E_NOMEM = 0, -1, -2, -3
 LBF_E_DEVICE, LBF_E_NONFINITE, LBF_E_STATE = -4, -5, -6
 LBF_D3Q19, LBF_D3Q27, LBF_D3Q27H = 19, 27, 270
-LBF_F64, LBF_F32, LBF_F16S, LBF_BF16S = 0, 1, 2, 3
+LBF_F64, LBF_F32, LBF_F16S, LBF_BF16S, LBF_F16SU = 0, 1, 2, 3, 4
 LBF_PERIODIC, LBF_WALLS = 0, 1
 LBF_ROUND_AUTO, LBF_ROUND_NEAREST, LBF_ROUND_STOCHASTIC = 0, 1, 2
 ROUNDING = {"auto": LBF_ROUND_AUTO, "nearest": LBF_ROUND_NEAREST,
             "stochastic": LBF_ROUND_STOCHASTIC}
 
-STORAGE = {"f64": LBF_F64, "f32": LBF_F32, "f16s": LBF_F16S, "bf16s": LBF_BF16S}
+STORAGE = {"f64": LBF_F64, "f32": LBF_F32, "f16s": LBF_F16S, "bf16s": LBF_BF16S,
+           "f16su": LBF_F16SU}
 LATTICE = {19: LBF_D3Q19, 27: LBF_D3Q27, "19": LBF_D3Q19, "27": LBF_D3Q27, "27h": LBF_D3Q27H,
            LBF_D3Q27H: LBF_D3Q27H}
 STATUS_NAMES = {0: "LBF_OK", -1: "LBF_E_ARG", -2: "LBF_E_UNSUPPORTED", -3: "LBF_E_NOMEM",

@@ -11,6 +11,7 @@ hipError_t launch_step_f64(int, int, bool, bool, const StepArgs&, hipStream_t);
 hipError_t launch_step_f32(int, int, bool, bool, const StepArgs&, hipStream_t);
 hipError_t launch_step_f16s(int, int, bool, bool, const StepArgs&, hipStream_t);
 hipError_t launch_step_bf16s(int, int, bool, bool, const StepArgs&, hipStream_t);
+hipError_t launch_step_f16su(int, int, bool, bool, const StepArgs&, hipStream_t);
 
 hipError_t launch_step_h_f64(int, bool, bool, const StepArgs&, hipStream_t);
 hipError_t launch_step_h_f32(int, bool, bool, const StepArgs&, hipStream_t);
@@ -34,6 +35,7 @@ hipError_t launch_step(int Q, int storage, int tile_rows, bool walls_y, const St
     case kF32: return launch_step_f32(Q, tile_rows, walls_y, ff, a, stream);
     case kF16S: return launch_step_f16s(Q, tile_rows, walls_y, ff, a, stream);
     case kBF16S: return launch_step_bf16s(Q, tile_rows, walls_y, ff, a, stream);
+    case kF16SU: return launch_step_f16su(Q, tile_rows, walls_y, ff, a, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -76,7 +78,13 @@ int grid_for(int64_t n) {
 template <int ST, typename U>
 __device__ __forceinline__ float stored_u(const U* u, int64_t i, float inv, float s) {
   using S = Storage<ST>;
-  return static_cast<float>(S::decode(S::encode(static_cast<typename S::C>(u[i]), inv), s));
+  if constexpr (S::kSplitU) {
+    typename S::T hi, lo;
+    S::split_unit(static_cast<float>(u[i]) * inv, hi, lo);
+    return S::join(hi, lo, s);
+  } else {
+    return static_cast<float>(S::decode(S::encode(static_cast<typename S::C>(u[i]), inv), s));
+  }
 }
 
 // user plane k (F64/F32) -> storage plane k; for deviation storage the planes
@@ -92,6 +100,15 @@ __global__ void encode_kernel(const U* __restrict__ user, const U* __restrict__ 
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < N;
        i += static_cast<int64_t>(gridDim.x) * kThreads) {
     C v = static_cast<C>(user[i]);
+    if constexpr (S::kSplitU) {
+      if (k >= 1 && k <= 3) {  // hi in plane k, lo in plane 9 + k
+        typename S::T hi, lo;
+        S::split_unit(v * inv.v[k], hi, lo);
+        __builtin_nontemporal_store(hi, buf + base + i);
+        __builtin_nontemporal_store(lo, buf + (9 + k) * N + i);
+        continue;
+      }
+    }
     if constexpr (S::kNeq) {
       if (k >= 4) {
         const U* ua = a2_a(k) == 0 ? u0 : (a2_a(k) == 1 ? u1 : u2);
@@ -112,11 +129,16 @@ __global__ void decode_kernel(const typename Storage<ST>::T* __restrict__ buf, U
   const int64_t base = static_cast<int64_t>(k) * N;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < N;
        i += static_cast<int64_t>(gridDim.x) * kThreads) {
-    auto v = S::load(buf, base + i, s.v[k]);
+    // velocity component c as stored (hi + lo for the split form)
+    auto vel = [&](int c) {
+      if constexpr (S::kSplitU)
+        return S::join(buf[(1 + c) * N + i], buf[(10 + c) * N + i], s.v[1 + c]);
+      else
+        return S::load(buf, (1 + c) * N + i, s.v[1 + c]);
+    };
+    auto v = (k >= 1 && k <= 3) ? vel(k - 1) : S::load(buf, base + i, s.v[k]);
     if constexpr (S::kNeq) {
-      if (k >= 4)
-        v += S::load(buf, (1 + a2_a(k)) * N + i, s.v[1 + a2_a(k)]) *
-             S::load(buf, (1 + a2_b(k)) * N + i, s.v[1 + a2_b(k)]);
+      if (k >= 4) v += vel(a2_a(k)) * vel(a2_b(k));
     }
     user[i] = static_cast<U>(v);
   }
@@ -160,10 +182,17 @@ __global__ void reduce_partial_kernel(const typename Storage<ST>::T* __restrict_
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < N;
        i += static_cast<int64_t>(gridDim.x) * kThreads) {
-    const double a0 = static_cast<double>(Storage<ST>::load(buf, i, s.v[0]));
-    const double ux = static_cast<double>(Storage<ST>::load(buf, N + i, s.v[1]));
-    const double uy = static_cast<double>(Storage<ST>::load(buf, 2 * N + i, s.v[2]));
-    const double uz = static_cast<double>(Storage<ST>::load(buf, 3 * N + i, s.v[3]));
+    using S = Storage<ST>;
+    double u3[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if constexpr (S::kSplitU)
+        u3[c] = static_cast<double>(S::join(buf[(1 + c) * N + i], buf[(10 + c) * N + i], s.v[1 + c]));
+      else
+        u3[c] = static_cast<double>(S::load(buf, (1 + c) * N + i, s.v[1 + c]));
+    }
+    const double a0 = static_cast<double>(S::load(buf, i, s.v[0]));
+    const double ux = u3[0], uy = u3[1], uz = u3[2];
     acc[0] += a0;
     acc[1] += ux;
     acc[2] += uy;
@@ -377,6 +406,7 @@ hipError_t launch_encode(int storage, int user_dtype, const void* plane, const v
     case kF32: return encode_st<kF32>(user_dtype, plane, u, buf, N, k, inv_scale, scale, s);
     case kF16S: return encode_st<kF16S>(user_dtype, plane, u, buf, N, k, inv_scale, scale, s);
     case kBF16S: return encode_st<kBF16S>(user_dtype, plane, u, buf, N, k, inv_scale, scale, s);
+    case kF16SU: return encode_st<kF16SU>(user_dtype, plane, u, buf, N, k, inv_scale, scale, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -388,6 +418,7 @@ hipError_t launch_decode(int storage, int user_dtype, const void* buf, void* pla
     case kF32: return decode_st<kF32>(user_dtype, buf, plane, N, k, scale, s);
     case kF16S: return decode_st<kF16S>(user_dtype, buf, plane, N, k, scale, s);
     case kBF16S: return decode_st<kBF16S>(user_dtype, buf, plane, N, k, scale, s);
+    case kF16SU: return decode_st<kF16SU>(user_dtype, buf, plane, N, k, scale, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -401,6 +432,8 @@ hipError_t launch_maxabs(int storage, int user_dtype, const void* plane, const v
     case kF16S: return maxabs_st<kF16S>(user_dtype, plane, u, N, k, inv_scale, scale, out_bits, s);
     case kBF16S:
       return maxabs_st<kBF16S>(user_dtype, plane, u, N, k, inv_scale, scale, out_bits, s);
+    case kF16SU:
+      return maxabs_st<kF16SU>(user_dtype, plane, u, N, k, inv_scale, scale, out_bits, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -412,6 +445,7 @@ hipError_t launch_reduce(int storage, const void* buf, int64_t N, const float* s
     case kF32: return reduce_st<kF32>(buf, N, scale, partials, out, s);
     case kF16S: return reduce_st<kF16S>(buf, N, scale, partials, out, s);
     case kBF16S: return reduce_st<kBF16S>(buf, N, scale, partials, out, s);
+    case kF16SU: return reduce_st<kF16SU>(buf, N, scale, partials, out, s);
     default: return hipErrorInvalidValue;
   }
 }

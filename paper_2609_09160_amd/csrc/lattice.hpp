@@ -97,7 +97,7 @@ __device__ __forceinline__ C div_by(C x) {
 }
 
 // storage codecs: element type in HBM (T) and compute type (C)
-enum { kF64 = 0, kF32 = 1, kF16S = 2, kBF16S = 3 };
+enum { kF64 = 0, kF32 = 1, kF16S = 2, kBF16S = 3, kF16SU = 4 };
 
 // lattice code of the D3Q27 set with the complete Hermite basis (the public
 // LBF_D3Q27H); the two truncated sets go by their velocity counts, 19 and 27
@@ -235,6 +235,8 @@ struct Storage<kF64> {
   using T = double;
   using C = double;
   static constexpr bool kNeq = false;
+  static constexpr int kPlanes = 10;
+  static constexpr bool kSplitU = false;
   static __device__ __forceinline__ C load(const T* p, int64_t i, float) { return p[i]; }
   static __device__ __forceinline__ C decode(T q, float) { return q; }
   static __device__ __forceinline__ T encode(C v, float) { return v; }
@@ -251,6 +253,8 @@ struct Storage<kF32> {
   using T = float;
   using C = float;
   static constexpr bool kNeq = false;
+  static constexpr int kPlanes = 10;
+  static constexpr bool kSplitU = false;
   static __device__ __forceinline__ C load(const T* p, int64_t i, float) { return p[i]; }
   static __device__ __forceinline__ C decode(T q, float) { return q; }
   static __device__ __forceinline__ T encode(C v, float) { return v; }
@@ -313,6 +317,8 @@ struct Storage<kF16S> {
   using T = uint16_t;
   using C = float;
   static constexpr bool kNeq = true;
+  static constexpr int kPlanes = 10;
+  static constexpr bool kSplitU = false;
   static __device__ __forceinline__ C load(const T* p, int64_t i, float s) {
     return f16_bits_to_f32(p[i]) * s;
   }
@@ -346,6 +352,8 @@ struct Storage<kBF16S> {
   using T = uint16_t;
   using C = float;
   static constexpr bool kNeq = true;
+  static constexpr int kPlanes = 10;
+  static constexpr bool kSplitU = false;
   static __device__ __forceinline__ C load(const T* p, int64_t i, float s) {
     return bf16_bits_to_f32(p[i]) * s;
   }
@@ -365,6 +373,29 @@ struct Storage<kBF16S> {
   static __device__ __forceinline__ void store_at(__amdgpu_buffer_rsrc_t r, uint32_t off, C v,
                                                  float inv_s) {
     buf_store_nt<T>(f32_to_bf16_bits(v * inv_s), r, off);
+  }
+};
+
+// FP16-scaled storage with the velocity split over two binary16 words: p*
+// and the six a2 - u u planes as in Storage<kF16S>, and each velocity
+// component u = s (hi + 2^-11 lo), hi its rounding to binary16 and lo the
+// rounding of the remainder, in three more planes (10..12).  The pair keeps
+// 22 significant bits of u, where the error of 16-bit storage comes from
+// almost entirely, for 13 x 2 bytes per site instead of 10 x 2.
+constexpr float kSplitLo = 1.0f / 2048.0f;  // scale of lo relative to hi
+template <>
+struct Storage<kF16SU> : Storage<kF16S> {
+  static constexpr int kPlanes = 13;
+  static constexpr bool kSplitU = true;
+  // value units (v / s) -> hi, lo; rounded to nearest even, the remainder
+  // un - hi is exact in binary32
+  static __device__ __forceinline__ void split_unit(C un, T& hi, T& lo) {
+    hi = f32_to_f16_bits(un);
+    lo = f32_to_f16_bits((un - f16_bits_to_f32(hi)) * 2048.0f);
+  }
+  // s (hi + 2^-11 lo), two exact products and one exact sum in the normal range
+  static __device__ __forceinline__ C join(T hi, T lo, float s) {
+    return decode(hi, s) + decode(lo, s * kSplitLo);
   }
 };
 

@@ -58,9 +58,18 @@ size_t elem_bytes(int storage) {
     case LBF_F64: return 8;
     case LBF_F32: return 4;
     case LBF_F16S:
-    case LBF_BF16S: return 2;
+    case LBF_BF16S:
+    case LBF_F16SU: return 2;
     default: return 0;
   }
+}
+
+// planes of one state buffer: the ten moments, plus the three low velocity
+// words of the split form
+size_t state_planes(int storage) { return storage == LBF_F16SU ? 13 : 10; }
+
+bool is_16bit(int storage) {
+  return storage == LBF_F16S || storage == LBF_BF16S || storage == LBF_F16SU;
 }
 
 bool is_pow2_float(float s) {
@@ -100,7 +109,7 @@ int validate(const lbfast_params* p) {
     return fail(LBF_E_ARG, "tau must be a finite value > 1/2 (got %g)", p->tau);
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(p->force[a])) return fail(LBF_E_ARG, "force[%d] is not finite", a);
-  const bool s16 = p->storage == LBF_F16S || p->storage == LBF_BF16S;
+  const bool s16 = is_16bit(p->storage);
   for (int k = 0; k < 10; ++k) {
     if (p->scale[k] == 0.0f) continue;
     if (!s16) return fail(LBF_E_ARG, "scale[] is only meaningful for 16-bit storage");
@@ -114,6 +123,12 @@ int validate(const lbfast_params* p) {
     return fail(LBF_E_ARG, "rounding must be LBF_ROUND_AUTO, _NEAREST or _STOCHASTIC");
   if (p->rounding == LBF_ROUND_STOCHASTIC && !s16)
     return fail(LBF_E_ARG, "stochastic rounding applies to 16-bit storage only");
+  if (p->storage == LBF_F16SU) {
+    if (p->rounding == LBF_ROUND_STOCHASTIC)
+      return fail(LBF_E_ARG, "LBF_F16SU rounds to nearest (its velocity keeps 22 bits)");
+    if (p->lattice == LBF_D3Q27H)
+      return fail(LBF_E_UNSUPPORTED, "LBF_F16SU storage is built for LBF_D3Q19 and LBF_D3Q27");
+  }
   return LBF_OK;
 }
 
@@ -377,7 +392,7 @@ int lbfast_abi_version(void) { return LBFAST_ABI_VERSION; }
 size_t lbfast_buffer_bytes(const lbfast_params* p) {
   if (validate(p) != LBF_OK) return 0;
   return static_cast<size_t>(p->nx) * static_cast<size_t>(p->ny) * static_cast<size_t>(p->nz) *
-         10u * elem_bytes(p->storage);
+         state_planes(p->storage) * elem_bytes(p->storage);
 }
 
 const char* lbfast_last_error(void) { return g_err.c_str(); }
@@ -444,7 +459,7 @@ int lbfast_create(const lbfast_params* p, void* stream, void* buf0, void* buf1, 
     h->scale[k] = (p->scale[k] != 0.0f) ? p->scale[k] : 1.0f;
     h->inv_scale[k] = 1.0f / h->scale[k];
   }
-  const bool s16 = p->storage == LBF_F16S || p->storage == LBF_BF16S;
+  const bool s16 = is_16bit(p->storage);
   h->scales_fixed = !s16;
   if (s16) {
     bool all = true;
@@ -786,6 +801,8 @@ int lbfast_enable_two_phase(lbfast_t h, const lbfast_phase_params* pp) {
     return fail(LBF_E_ARG, "phase relaxation times must be finite and > 1/2");
   if (h->p.bc[0] != LBF_PERIODIC || h->p.bc[2] != LBF_PERIODIC)
     return fail(LBF_E_UNSUPPORTED, "walls are supported on the y axis only");
+  if (h->p.storage == LBF_F16SU)
+    return fail(LBF_E_UNSUPPORTED, "the two-component variant does not cover LBF_F16SU storage");
   if (h->Ffield) return fail(LBF_E_STATE, "a per-site force field is set");
   if (h->two_phase) return fail(LBF_E_STATE, "two-component variant already enabled");
   DeviceGuard g(h->device);

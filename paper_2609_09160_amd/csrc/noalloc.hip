@@ -52,7 +52,8 @@ extern "C" int lbfast_reduce_noalloc(const void* state_dev, int storage, int64_t
                                      const float scale[10], double* out_dev, void* stream) {
   lbf::clear_error();
   if (!state_dev || !out_dev) return fail(LBF_E_ARG, "state_dev and out_dev are required");
-  if (storage != LBF_F64 && storage != LBF_F32 && storage != LBF_F16S && storage != LBF_BF16S)
+  if (storage != LBF_F64 && storage != LBF_F32 && storage != LBF_F16S && storage != LBF_BF16S &&
+      storage != LBF_F16SU)
     return fail(LBF_E_ARG, "unknown storage");
   if (n_sites < 1 || static_cast<double>(n_sites) > 4.0e9)
     return fail(LBF_E_ARG, "n_sites must be in [1, 4e9] (the largest grid lbfast_create accepts)");
@@ -60,7 +61,7 @@ extern "C" int lbfast_reduce_noalloc(const void* state_dev, int storage, int64_t
   if (reinterpret_cast<uintptr_t>(state_dev) & (eb - 1))
     return fail(LBF_E_ARG, "state_dev is not aligned to its element size");
   if (reinterpret_cast<uintptr_t>(out_dev) & 7) return fail(LBF_E_ARG, "out_dev is misaligned");
-  const bool s16 = storage == LBF_F16S || storage == LBF_BF16S;
+  const bool s16 = storage == LBF_F16S || storage == LBF_BF16S || storage == LBF_F16SU;
   if (s16 && !scale) return fail(LBF_E_ARG, "16-bit storage needs its ten scales");
   if (!device_memory(state_dev) || !device_memory(out_dev))
     return fail(LBF_E_ARG, "state_dev and out_dev must be device memory");

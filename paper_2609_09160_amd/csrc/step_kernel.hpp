@@ -257,7 +257,7 @@ struct Forward {
   // with variable properties, phi(t)
   template <bool OWN>
   struct Raw {
-    T m[10];
+    T m[S::kPlanes];
     C F[3];
     C sc;
     C ph;
@@ -289,7 +289,7 @@ struct Forward {
                                                uint32_t plane_bytes, Raw<OWN> (&r)[NS]) {
     const T* __restrict__ src = static_cast<const T*>(a.src);
 #pragma unroll
-    for (int k = 0; k < 10; ++k) {
+    for (int k = 0; k < S::kPlanes; ++k) {
       T v[NS];
       buf_load_n<T, NS>(plane_rsrc(src + (k * a.N + pb), plane_bytes), off, v);
 #pragma unroll
@@ -336,6 +336,10 @@ struct Forward {
       if constexpr (kNeqMode == kDevRelaxed)
         sk = k >= 4 ? (1.0f - static_cast<float>(a.omega)) * sk : sk;
       m[k] = S::decode(r.m[k], sk);
+    }
+    if constexpr (S::kSplitU) {
+#pragma unroll
+      for (int k = 1; k < 4; ++k) m[k] = S::join(r.m[k], r.m[9 + k], a.scale[k]);
     }
     C F[3];
 #pragma unroll
@@ -429,7 +433,7 @@ struct Forward {
                                                 uint32_t plane_bytes) {
     T* __restrict__ dst = static_cast<T*>(a.dst);
     C out[NS][10];
-    T q[NS][10];
+    T q[NS][S::kPlanes];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       finalize<Q, C, !NOF>(acc[s], c[s].F[0], c[s].F[1], c[s].F[2], out[s]);
@@ -454,18 +458,29 @@ struct Forward {
             un[k] = out[s][k] * a.inv_scale[k];
           }
         }
-        if (a.stochastic) {
-          const uint32_t site = static_cast<uint32_t>(pb) + off / sizeof(T) + s;
-          const uint32_t h = hash32(site ^ a.sr_seed);
-#pragma unroll
-          for (int k = 0; k < 4; ++k) q[s][k] = S::encode_unit_sr(un[k], (h >> (8 * k)) & 0xffu);
-        } else {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) q[s][k] = S::encode_unit(un[k]);
-        }
         C ur[3];
+        if constexpr (S::kSplitU) {
+          // split velocity (always to nearest): u as hi and lo words
+          q[s][0] = S::encode_unit(un[0]);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) ur[k] = S::decode(q[s][1 + k], a.scale[1 + k]);
+          for (int k = 1; k < 4; ++k) {
+            S::split_unit(un[k], q[s][k], q[s][9 + k]);
+            ur[k - 1] = S::join(q[s][k], q[s][9 + k], a.scale[k]);
+          }
+        } else {
+          if (a.stochastic) {
+            const uint32_t site = static_cast<uint32_t>(pb) + off / sizeof(T) + s;
+            const uint32_t h = hash32(site ^ a.sr_seed);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+              q[s][k] = S::encode_unit_sr(un[k], (h >> (8 * k)) & 0xffu);
+          } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) q[s][k] = S::encode_unit(un[k]);
+          }
+#pragma unroll
+          for (int k = 0; k < 3; ++k) ur[k] = S::decode(q[s][1 + k], a.scale[1 + k]);
+        }
 #pragma unroll
         for (int k = 4; k < 10; ++k)
           q[s][k] = S::encode(out[s][k] - ur[a2_a(k)] * ur[a2_b(k)], a.inv_scale[k]);
@@ -475,7 +490,7 @@ struct Forward {
       }
     }
 #pragma unroll
-    for (int k = 0; k < 10; ++k) {
+    for (int k = 0; k < S::kPlanes; ++k) {
       T v[NS];
 #pragma unroll
       for (int s = 0; s < NS; ++s) v[s] = q[s][k];

@@ -15,7 +15,8 @@ class Solver:
     """One moment-represented LBM lattice on one GPU.
 
     shape = (nx, ny, nz); lattice in {19, 27, "27h"} ("27h": the D3Q27 set
-    with the complete Hermite basis); storage in {"f64", "f32", "f16s", "bf16s"};
+    with the complete Hermite basis); storage in {"f64", "f32", "f16s", "bf16s",
+    "f16su"} ("f16su": FP16 with the velocity split over two 16-bit words);
     bc = per-axis 0 (periodic) / 1 (walls, y only); force = uniform body force;
     rounding = "auto" (FP16 to nearest, BF16 stochastic), "nearest" or
     "stochastic" (16-bit storage: how the step rounds p* and u).

@@ -22,19 +22,22 @@ def _cuda():
 
 @pytest.mark.parametrize("sites", [1, 2])
 @pytest.mark.parametrize("Q", [19, 27, "27h"])
-@pytest.mark.parametrize("storage,bound", [("f16s", 1e-3), ("bf16s", 3e-2)])
+@pytest.mark.parametrize("storage,bound", [("f16s", 1e-3), ("bf16s", 3e-2), ("f16su", 2e-4)])
 def test_16bit_storage_accuracy(Q, storage, bound, sites):
     """16-bit scaled moment storage (FP32 arithmetic), 64^3 solenoidal workload,
     tau = 0.6, 1000 steps: relative L2 error of u against the FP64 oracle, with
     one and with two x-sites per lane (two is the form the 512^3 benchmark
     runs; at 64^3 the default is one).
     FP16 (11-bit significand) meets the 1e-3 bar stated for the 16-bit form.
-    BF16 (8-bit significand) cannot: u itself is re-rounded every step with
+    FP16 with the velocity split over two words (22 bits for u) is held to
+    2e-4.  BF16 (8-bit significand) cannot: u itself is re-rounded every step with
     unit roundoff 2^-9 ~ 2e-3.  Rounded to nearest, the low-wavenumber part of
     that error accumulates over 1000 steps like a random walk (sqrt(1000) *
     2e-3 ~ 6e-2); BF16's default, stochastic rounding, makes each rounding
     unbiased and independent, and the error settles near 1.2e-2; it is held
     to 3e-2."""
+    if storage == "f16su" and Q == "27h":
+        pytest.skip("the split-velocity form is built for the second-order sets")
     n = 64
     m0, want = solenoidal_oracle_1000(Q, n)
     got = gpu_run((n, n, n), 0.6, m0, 1000, lattice=Q, storage=storage, launch=(0, 0, sites))
@@ -82,8 +85,10 @@ def test_storage_forms_512_vs_fp64(Q):
     torch.cuda.empty_cache()
     ref_norm = float(torch.linalg.vector_norm(ref))
     bars = {("f32", "auto"): 1e-5, ("f16s", "nearest"): 4e-3, ("f16s", "stochastic"): 2.5e-3,
-            ("bf16s", "stochastic"): 3e-2}
+            ("bf16s", "stochastic"): 3e-2, ("f16su", "auto"): 1e-3}
     for (storage, rounding), bar in bars.items():
+        if storage == "f16su" and Q == "27h":
+            continue  # the split-velocity form is built for the second-order sets
         u = u_after(storage, rounding)
         e = float(torch.linalg.vector_norm(u - ref)) / ref_norm
         del u
@@ -94,7 +99,7 @@ def test_storage_forms_512_vs_fp64(Q):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("storage,bound", [("f16s", 2e-3), ("bf16s", 1.6e-2)])
+@pytest.mark.parametrize("storage,bound", [("f16s", 2e-3), ("bf16s", 1.6e-2), ("f16su", 2e-3)])
 @pytest.mark.parametrize("Q", [19, 27, "27h"])
 def test_sampled_sites_512_16bit(Q, storage, bound):
     """Full size, bench launch configuration, 16-bit storage with its default
@@ -107,6 +112,8 @@ def test_sampled_sites_512_16bit(Q, storage, bound):
     twice that."""
     import torch
     from paper_2609_09160_amd import Solver
+    if storage == "f16su" and Q == "27h":
+        pytest.skip("the split-velocity form is built for the second-order sets")
     n, tau = 512, 0.6
     m32 = inputs.solenoidal_field((n, n, n), device="cuda").float()
     s = Solver((n, n, n), tau, lattice=Q, storage=storage)

@@ -59,6 +59,20 @@ def test_memory_model_matches_paper(lib):
     for st in ("f16s", "bf16s"):
         p = _lib.make_params((512, 512, 512), 0.6, storage=st)
         assert 2 * lib.lbfast_buffer_bytes(ctypes.byref(p)) / GiB == 5.0
+    # the split-velocity form: ten 16-bit moment planes plus three low words
+    p = _lib.make_params((512, 512, 512), 0.6, storage="f16su")
+    assert lib.lbfast_buffer_bytes(ctypes.byref(p)) == N * 13 * 2
+
+
+@pytest.mark.parametrize("lattice,rounding,code,needle", [
+    ("27h", "auto", _lib.LBF_E_UNSUPPORTED, "LBF_D3Q19 and LBF_D3Q27"),
+    (19, "stochastic", _lib.LBF_E_ARG, "nearest"),
+])
+def test_split_storage_validation(lib, lattice, rounding, code, needle):
+    p = _lib.make_params((32, 8, 8), 0.7, lattice=lattice, storage="f16su", rounding=rounding)
+    assert lib.lbfast_buffer_bytes(ctypes.byref(p)) == 0
+    rc, msg = _create(lib, p)
+    assert rc == code and needle in msg
 
 
 def _create(lib, p, bufs=(None, None)):

@@ -32,7 +32,7 @@ def _noalloc(s, out_dev):
     return out_dev.cpu().numpy().copy()
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s", "f16su"])
 def test_noalloc_reduce_matches_reduce(storage):
     import torch
     out_dev = torch.full((5,), float("nan"), dtype=torch.float64, device="cuda")
