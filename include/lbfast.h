@@ -84,9 +84,15 @@ enum { LBF_D3Q19 = 19, LBF_D3Q27 = 27, LBF_D3Q27H = 270 };
  * u = s_u (hi + 2^-11 lo), hi the rounding of u/s_u and lo that of the
  * remainder (both to nearest even): 22 significant bits for u, which carries
  * almost all of the 16-bit storage error of a slowly evolving flow.  A state
- * buffer then holds 13 planes of N binary16 words: the ten moment planes
- * (planes 1..3 the hi words), then the lo words of u_x, u_y, u_z.  LBF_D3Q19
- * and LBF_D3Q27 only, one component, rounding to nearest only. */
+ * then holds 13 planes of N binary16 words: the ten moment planes (planes
+ * 1..3 the hi words), then the lo words of u_x, u_y, u_z.  LBF_D3Q19 and
+ * LBF_D3Q27 only, one component, rounding to nearest only.
+ * Layout of a 16-bit state (what lbfast_state_ptr points to): planes 2j and
+ * 2j + 1 share the 4 N bytes at offset 4 j N, interleaved by site, so that
+ * the 32-bit word at offset 4 (j N + i) holds plane 2j of site i in its low
+ * half and plane 2j + 1 in its high half; a last odd plane (plane 12 of
+ * F16SU) is N plain binary16 words at offset 2 (12 N).  FP32 and FP64 states
+ * are plane after plane: plane k of site i at element k N + i. */
 enum { LBF_F64 = 0, LBF_F32 = 1, LBF_F16S = 2, LBF_BF16S = 3, LBF_F16SU = 4 };
 
 /* boundary per axis: periodic, or stationary halfway bounce-back walls at
@@ -189,9 +195,9 @@ int lbfast_reduce(lbfast_t h, double out[5]);
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the sums of
  * lbfast_reduce over any moment array, with no handle and no allocation.
- *   state_dev  10 x n_sites values in the storage format `storage`
- *              (LBF_F64, LBF_F32, LBF_F16S, LBF_BF16S; 13 x n_sites for
- *              LBF_F16SU), device memory, e.g. lbfast_state_ptr() or a
+ *   state_dev  10 x n_sites values in the storage format and layout of
+ *              `storage` (LBF_F64, LBF_F32, LBF_F16S, LBF_BF16S; 13 x n_sites
+ *              for LBF_F16SU), device memory, e.g. lbfast_state_ptr() or a
  *              checkpoint slot; read only;
  *   scale      the ten 16-bit storage scales (lbfast_get_scales), host array;
  *              required for 16-bit storage, ignored (may be NULL) otherwise;

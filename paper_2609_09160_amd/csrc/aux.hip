@@ -96,7 +96,6 @@ __global__ void encode_kernel(const U* __restrict__ user, const U* __restrict__ 
                               Scales inv, Scales fwd) {
   using S = Storage<ST>;
   using C = typename S::C;
-  const int64_t base = static_cast<int64_t>(k) * N;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < N;
        i += static_cast<int64_t>(gridDim.x) * kThreads) {
     C v = static_cast<C>(user[i]);
@@ -104,8 +103,8 @@ __global__ void encode_kernel(const U* __restrict__ user, const U* __restrict__ 
       if (k >= 1 && k <= 3) {  // hi in plane k, lo in plane 9 + k
         typename S::T hi, lo;
         S::split_unit(v * inv.v[k], hi, lo);
-        __builtin_nontemporal_store(hi, buf + base + i);
-        __builtin_nontemporal_store(lo, buf + (9 + k) * N + i);
+        __builtin_nontemporal_store(hi, buf + plane_elem<S>(k, i, N));
+        __builtin_nontemporal_store(lo, buf + plane_elem<S>(9 + k, i, N));
         continue;
       }
     }
@@ -117,7 +116,7 @@ __global__ void encode_kernel(const U* __restrict__ user, const U* __restrict__ 
                             stored_u<ST>(ub, i, inv.v[1 + a2_b(k)], fwd.v[1 + a2_b(k)]));
       }
     }
-    S::store(buf, base + i, v, inv.v[k]);
+    S::store(buf, plane_elem<S>(k, i, N), v, inv.v[k]);
   }
 }
 
@@ -126,17 +125,17 @@ template <int ST, typename U>
 __global__ void decode_kernel(const typename Storage<ST>::T* __restrict__ buf, U* __restrict__ user,
                               int64_t N, int k, Scales s) {
   using S = Storage<ST>;
-  const int64_t base = static_cast<int64_t>(k) * N;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < N;
        i += static_cast<int64_t>(gridDim.x) * kThreads) {
     // velocity component c as stored (hi + lo for the split form)
     auto vel = [&](int c) {
       if constexpr (S::kSplitU)
-        return S::join(buf[(1 + c) * N + i], buf[(10 + c) * N + i], s.v[1 + c]);
+        return S::join(buf[plane_elem<S>(1 + c, i, N)], buf[plane_elem<S>(10 + c, i, N)],
+                       s.v[1 + c]);
       else
-        return S::load(buf, (1 + c) * N + i, s.v[1 + c]);
+        return S::load(buf, plane_elem<S>(1 + c, i, N), s.v[1 + c]);
     };
-    auto v = (k >= 1 && k <= 3) ? vel(k - 1) : S::load(buf, base + i, s.v[k]);
+    auto v = (k >= 1 && k <= 3) ? vel(k - 1) : S::load(buf, plane_elem<S>(k, i, N), s.v[k]);
     if constexpr (S::kNeq) {
       if (k >= 4) v += vel(a2_a(k)) * vel(a2_b(k));
     }
@@ -187,11 +186,12 @@ __global__ void reduce_partial_kernel(const typename Storage<ST>::T* __restrict_
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       if constexpr (S::kSplitU)
-        u3[c] = static_cast<double>(S::join(buf[(1 + c) * N + i], buf[(10 + c) * N + i], s.v[1 + c]));
+        u3[c] = static_cast<double>(S::join(buf[plane_elem<S>(1 + c, i, N)],
+                                            buf[plane_elem<S>(10 + c, i, N)], s.v[1 + c]));
       else
-        u3[c] = static_cast<double>(S::load(buf, (1 + c) * N + i, s.v[1 + c]));
+        u3[c] = static_cast<double>(S::load(buf, plane_elem<S>(1 + c, i, N), s.v[1 + c]));
     }
-    const double a0 = static_cast<double>(S::load(buf, i, s.v[0]));
+    const double a0 = static_cast<double>(S::load(buf, plane_elem<S>(0, i, N), s.v[0]));
     const double ux = u3[0], uy = u3[1], uz = u3[2];
     acc[0] += a0;
     acc[1] += ux;

@@ -237,6 +237,7 @@ struct Storage<kF64> {
   static constexpr bool kNeq = false;
   static constexpr int kPlanes = 10;
   static constexpr bool kSplitU = false;
+  static constexpr bool kPaired = false;
   static __device__ __forceinline__ C load(const T* p, int64_t i, float) { return p[i]; }
   static __device__ __forceinline__ C decode(T q, float) { return q; }
   static __device__ __forceinline__ T encode(C v, float) { return v; }
@@ -255,6 +256,7 @@ struct Storage<kF32> {
   static constexpr bool kNeq = false;
   static constexpr int kPlanes = 10;
   static constexpr bool kSplitU = false;
+  static constexpr bool kPaired = false;
   static __device__ __forceinline__ C load(const T* p, int64_t i, float) { return p[i]; }
   static __device__ __forceinline__ C decode(T q, float) { return q; }
   static __device__ __forceinline__ T encode(C v, float) { return v; }
@@ -319,6 +321,7 @@ struct Storage<kF16S> {
   static constexpr bool kNeq = true;
   static constexpr int kPlanes = 10;
   static constexpr bool kSplitU = false;
+  static constexpr bool kPaired = true;
   static __device__ __forceinline__ C load(const T* p, int64_t i, float s) {
     return f16_bits_to_f32(p[i]) * s;
   }
@@ -354,6 +357,7 @@ struct Storage<kBF16S> {
   static constexpr bool kNeq = true;
   static constexpr int kPlanes = 10;
   static constexpr bool kSplitU = false;
+  static constexpr bool kPaired = true;
   static __device__ __forceinline__ C load(const T* p, int64_t i, float s) {
     return bf16_bits_to_f32(p[i]) * s;
   }
@@ -398,6 +402,21 @@ struct Storage<kF16SU> : Storage<kF16S> {
     return decode(hi, s) + decode(lo, s * kSplitLo);
   }
 };
+
+// Element index of moment plane k at site i, in a state of N sites.  With
+// kPaired (16-bit storage) planes 2j and 2j + 1 share the space of the two
+// planes, interleaved site by site: one 32-bit word holds both values of a
+// site, plane 2j in its low half.  A last, odd plane stays on its own.  A
+// wave then reads half as many, twice as wide streams: a z-march copy of ten
+// 16-bit planes in this order moved 5.2 TB/s against 4.7 with the planes
+// apart (MI355X, 512^3, 2 sites per lane).
+template <typename S>
+__host__ __device__ constexpr int64_t plane_elem(int k, int64_t i, int64_t N) {
+  if constexpr (S::kPaired) {
+    if (k < (S::kPlanes & ~1)) return static_cast<int64_t>(k & ~1) * N + 2 * i + (k & 1);
+  }
+  return static_cast<int64_t>(k) * N + i;
+}
 
 // index pairs (a, b) of the second-order planes 4..9: xx, yy, zz, xy, xz, yz
 __host__ __device__ constexpr int a2_a(int k) { return k <= 6 ? k - 4 : (k == 9 ? 1 : 0); }

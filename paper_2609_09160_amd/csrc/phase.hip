@@ -167,9 +167,20 @@ __global__ void __launch_bounds__(64 * kUpdRows) phase_kernel(
       const int64_t zu = static_cast<int64_t>(pmod(clampi(qs + i - 1, z0 - 1, z1), nz)) * plane;
 #pragma unroll
       for (int k = 0; k < PERV; ++k) {
-        ux[b][i][k] = S::decode(buf_load<typename S::T>(plane_rsrc(st + N + zu, pbytes_t), voff[k]), s1);
-        uy[b][i][k] = S::decode(buf_load<typename S::T>(plane_rsrc(st + 2 * N + zu, pbytes_t), voff[k]), s2);
-        uz[b][i][k] = S::decode(buf_load<typename S::T>(plane_rsrc(st + 3 * N + zu, pbytes_t), voff[k]), s3);
+        if constexpr (S::kPaired) {
+          // 16-bit storage: (p*, u_x) and (u_y, u_z) are one 32-bit word each
+          using T = typename S::T;
+          const uint32_t* st32 = reinterpret_cast<const uint32_t*>(st);
+          const uint32_t w0 = buf_load<uint32_t>(plane_rsrc(st32 + zu, 2 * pbytes_t), 2 * voff[k]);
+          const uint32_t w1 = buf_load<uint32_t>(plane_rsrc(st32 + N + zu, 2 * pbytes_t), 2 * voff[k]);
+          ux[b][i][k] = S::decode(static_cast<T>(w0 >> 16), s1);
+          uy[b][i][k] = S::decode(static_cast<T>(w1 & 0xffffu), s2);
+          uz[b][i][k] = S::decode(static_cast<T>(w1 >> 16), s3);
+        } else {
+          ux[b][i][k] = S::decode(buf_load<typename S::T>(plane_rsrc(st + N + zu, pbytes_t), voff[k]), s1);
+          uy[b][i][k] = S::decode(buf_load<typename S::T>(plane_rsrc(st + 2 * N + zu, pbytes_t), voff[k]), s2);
+          uz[b][i][k] = S::decode(buf_load<typename S::T>(plane_rsrc(st + 3 * N + zu, pbytes_t), voff[k]), s3);
+        }
       }
     });
   };
@@ -312,7 +323,7 @@ struct ForceEmit {
   __device__ __forceinline__ void prefetch(int64_t s, Pre& pre) const {
     if constexpr (CONTRAST) {
 #pragma unroll
-      for (int k = 0; k < 10; ++k) pre.m[k] = S::load(st + k * N, s, pa.scale[k]);
+      for (int k = 0; k < 10; ++k) pre.m[k] = S::load(st, plane_elem<S>(k, s, N), pa.scale[k]);
     }
   }
   __device__ __forceinline__ void operator()(int64_t s, C p, const C g[3], C l,

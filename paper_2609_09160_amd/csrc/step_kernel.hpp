@@ -281,6 +281,8 @@ struct Forward {
     for (int k = 0; k < ((FNEXT && VAR) ? 6 : 1); ++k) c.M[k] = C(0);
   }
 
+  // two 16-bit words of one site (paired planes 2j, 2j + 1)
+  using T2 = T __attribute__((ext_vector_type(2)));
   // the force field has the compute type; its byte offset scales accordingly
   static constexpr uint32_t kFscale = sizeof(C) / sizeof(T);
 
@@ -288,8 +290,25 @@ struct Forward {
   static __device__ __forceinline__ void fetch(const StepArgs& a, int64_t pb, uint32_t off,
                                                uint32_t plane_bytes, Raw<OWN> (&r)[NS]) {
     const T* __restrict__ src = static_cast<const T*>(a.src);
+    // 16-bit storage: planes 2j and 2j + 1 as one 32-bit word per site
+    constexpr int kWords = S::kPaired ? S::kPlanes / 2 : 0;
+    if constexpr (S::kPaired) {
 #pragma unroll
-    for (int k = 0; k < S::kPlanes; ++k) {
+      for (int j = 0; j < kWords; ++j) {
+        uint32_t w[NS];
+        buf_load_n<uint32_t, NS>(
+            plane_rsrc(reinterpret_cast<const uint32_t*>(src) + (j * a.N + pb), 2 * plane_bytes),
+            2 * off, w);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const T2 h = __builtin_bit_cast(T2, w[s]);
+          r[s].m[2 * j] = h.x;
+          r[s].m[2 * j + 1] = h.y;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 2 * kWords; k < S::kPlanes; ++k) {
       T v[NS];
       buf_load_n<T, NS>(plane_rsrc(src + (k * a.N + pb), plane_bytes), off, v);
 #pragma unroll
@@ -489,8 +508,23 @@ struct Forward {
         for (int k = 0; k < 10; ++k) q[s][k] = S::encode(out[s][k], a.inv_scale[k]);
       }
     }
+    constexpr int kWords = S::kPaired ? S::kPlanes / 2 : 0;
+    if constexpr (S::kPaired) {
 #pragma unroll
-    for (int k = 0; k < S::kPlanes; ++k) {
+      for (int j = 0; j < kWords; ++j) {
+        uint32_t w[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const T2 h = {q[s][2 * j], q[s][2 * j + 1]};  // one packed conversion
+          w[s] = __builtin_bit_cast(uint32_t, h);
+        }
+        buf_store_nt_n<uint32_t, NS>(
+            w, plane_rsrc(reinterpret_cast<uint32_t*>(dst) + (j * a.N + pb), 2 * plane_bytes),
+            2 * off);
+      }
+    }
+#pragma unroll
+    for (int k = 2 * kWords; k < S::kPlanes; ++k) {
       T v[NS];
 #pragma unroll
       for (int s = 0; s < NS; ++s) v[s] = q[s][k];

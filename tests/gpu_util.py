@@ -30,6 +30,21 @@ def gpu_run(shape, tau, m0, steps, lattice=19, storage="f64", bc=(0, 0, 0), forc
     return out
 
 
+def stored_planes(words, nplanes, N):
+    """The binary16 words of a 16-bit state as [nplanes, N], plane by plane,
+    from the layout the library documents: planes 2j and 2j + 1 interleaved
+    site by site in words [2jN, (2j + 2)N), plane 2j first (the low half of
+    each 32-bit word); a last odd plane on its own after them."""
+    words = np.asarray(words).reshape(-1)[:nplanes * N]
+    out = np.empty((nplanes, N), dtype=words.dtype)
+    for j in range(nplanes // 2):
+        pair = words[2 * j * N:(2 * j + 2) * N].reshape(N, 2)
+        out[2 * j], out[2 * j + 1] = pair[:, 0], pair[:, 1]
+    if nplanes % 2:
+        out[-1] = words[(nplanes - 1) * N:nplanes * N]
+    return out
+
+
 def oracle_run(shape, tau, m0, steps, lattice=19, bc=(0, 0, 0), force=None):
     import oracle
     o = oracle.PopulationOracle(lattice, shape, tau, bc=bc, force=force)

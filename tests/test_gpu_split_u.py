@@ -8,7 +8,7 @@ import pytest
 
 from paper_2609_09160_amd import inputs
 
-from gpu_util import gpu_run, group_rel_err, oracle_run, say
+from gpu_util import gpu_run, group_rel_err, oracle_run, say, stored_planes
 
 pytestmark = pytest.mark.gpu
 
@@ -39,7 +39,7 @@ def test_split_words_and_roundtrip():
     ptr = s.state_ptr()
     buf = [b for b in s._bufs if b.data_ptr() == ptr]
     assert len(buf) == 1 and buf[0].numel() == 13 * N * 2
-    words = buf[0].cpu().numpy().view(np.uint16).reshape(13, N)
+    words = stored_planes(buf[0].cpu().numpy().view(np.uint16), 13, N)
     for c in range(3):
         x = (m[1 + c].reshape(-1).astype(np.float32) * np.float32(1.0 / sc[1 + c]))
         hi = x.astype(np.float16)

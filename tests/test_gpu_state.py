@@ -7,7 +7,7 @@ import pytest
 
 from paper_2609_09160_amd import inputs
 
-from gpu_util import say
+from gpu_util import say, stored_planes
 
 pytestmark = pytest.mark.gpu
 
@@ -106,7 +106,7 @@ def test_16bit_encoding_bit_exact(storage):
     ptr = s.state_ptr()
     buf = [b for b in s._bufs if b.data_ptr() == ptr]
     assert len(buf) == 1
-    words = buf[0][:10 * N * 2].cpu().numpy().view(np.uint16).reshape(10, N)
+    words = stored_planes(buf[0][:10 * N * 2].cpu().numpy().view(np.uint16), 10, N)
     for k in range(4):
         x = m[k].reshape(-1).astype(np.float32)
         if storage == "f16s":
@@ -117,6 +117,19 @@ def test_16bit_encoding_bit_exact(storage):
         bad = int((words[k] != want).sum())
         say(f"{storage} plane {k}: {bad} of {N} words differ")
         assert bad == 0
+    # the step writes the same layout: p* and u read back from its stored
+    # words on the host (scale 1) equal what the library decodes
+    s.step(1)
+    ptr = s.state_ptr()
+    buf = [b for b in s._bufs if b.data_ptr() == ptr]
+    words = stored_planes(buf[0][:10 * N * 2].cpu().numpy().view(np.uint16), 10, N)
+    got = s.moments_host()
+    for k in range(4):
+        if storage == "f16s":
+            host = words[k].view(np.float16).astype(np.float64)
+        else:
+            host = (words[k].astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+        assert np.array_equal(host, got[k].reshape(-1)), f"{storage} plane {k} after a step"
     s.close()
 
 
