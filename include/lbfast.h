@@ -87,12 +87,14 @@ enum { LBF_D3Q19 = 19, LBF_D3Q27 = 27, LBF_D3Q27H = 270 };
  * then holds 13 planes of N binary16 words: the ten moment planes (planes
  * 1..3 the hi words), then the lo words of u_x, u_y, u_z.  LBF_D3Q19 and
  * LBF_D3Q27 only, one component, rounding to nearest only.
- * Layout of a 16-bit state (what lbfast_state_ptr points to): planes 2j and
- * 2j + 1 share the 4 N bytes at offset 4 j N, interleaved by site, so that
- * the 32-bit word at offset 4 (j N + i) holds plane 2j of site i in its low
- * half and plane 2j + 1 in its high half; a last odd plane (plane 12 of
- * F16SU) is N plain binary16 words at offset 2 (12 N).  FP32 and FP64 states
- * are plane after plane: plane k of site i at element k N + i. */
+ * Layout of a 16-bit state (what lbfast_state_ptr points to): planes 4j ..
+ * 4j + 3 share the 8 N bytes at offset 8 j N, interleaved by site: the 64-bit
+ * word at offset 8 (j N + i) holds the four values of site i, plane 4j in its
+ * lowest 16 bits.  Two planes left over (8 and 9 of F16S and BF16S) share the
+ * 4 N bytes after the groups the same way, one 32-bit word per site, the lower
+ * plane in its low half; a last single plane (12 of F16SU) is N plain
+ * binary16 words at offset 2 (12 N).  FP32 and FP64 states are plane after
+ * plane: plane k of site i at element k N + i. */
 enum { LBF_F64 = 0, LBF_F32 = 1, LBF_F16S = 2, LBF_BF16S = 3, LBF_F16SU = 4 };
 
 /* boundary per axis: periodic, or stationary halfway bounce-back walls at

@@ -237,7 +237,7 @@ struct Storage<kF64> {
   static constexpr bool kNeq = false;
   static constexpr int kPlanes = 10;
   static constexpr bool kSplitU = false;
-  static constexpr bool kPaired = false;
+  static constexpr bool kGrouped = false;
   static __device__ __forceinline__ C load(const T* p, int64_t i, float) { return p[i]; }
   static __device__ __forceinline__ C decode(T q, float) { return q; }
   static __device__ __forceinline__ T encode(C v, float) { return v; }
@@ -256,7 +256,7 @@ struct Storage<kF32> {
   static constexpr bool kNeq = false;
   static constexpr int kPlanes = 10;
   static constexpr bool kSplitU = false;
-  static constexpr bool kPaired = false;
+  static constexpr bool kGrouped = false;
   static __device__ __forceinline__ C load(const T* p, int64_t i, float) { return p[i]; }
   static __device__ __forceinline__ C decode(T q, float) { return q; }
   static __device__ __forceinline__ T encode(C v, float) { return v; }
@@ -321,7 +321,7 @@ struct Storage<kF16S> {
   static constexpr bool kNeq = true;
   static constexpr int kPlanes = 10;
   static constexpr bool kSplitU = false;
-  static constexpr bool kPaired = true;
+  static constexpr bool kGrouped = true;
   static __device__ __forceinline__ C load(const T* p, int64_t i, float s) {
     return f16_bits_to_f32(p[i]) * s;
   }
@@ -357,7 +357,7 @@ struct Storage<kBF16S> {
   static constexpr bool kNeq = true;
   static constexpr int kPlanes = 10;
   static constexpr bool kSplitU = false;
-  static constexpr bool kPaired = true;
+  static constexpr bool kGrouped = true;
   static __device__ __forceinline__ C load(const T* p, int64_t i, float s) {
     return bf16_bits_to_f32(p[i]) * s;
   }
@@ -404,16 +404,21 @@ struct Storage<kF16SU> : Storage<kF16S> {
 };
 
 // Element index of moment plane k at site i, in a state of N sites.  With
-// kPaired (16-bit storage) planes 2j and 2j + 1 share the space of the two
-// planes, interleaved site by site: one 32-bit word holds both values of a
-// site, plane 2j in its low half.  A last, odd plane stays on its own.  A
-// wave then reads half as many, twice as wide streams: a z-march copy of ten
-// 16-bit planes in this order moved 5.2 TB/s against 4.7 with the planes
-// apart (MI355X, 512^3, 2 sites per lane).
+// kGrouped (16-bit storage) the planes go in groups of four, 4j .. 4j + 3,
+// interleaved site by site in the space of the four planes: one 64-bit word
+// holds the four values of a site, plane 4j in its lowest 16 bits.  Two
+// planes left over form a pair the same way (one 32-bit word per site); a
+// last odd plane stays on its own.  A wave then reads a few wide streams
+// instead of many narrow ones: z-march copies of ten 16-bit planes (2 sites
+// per lane, 512^3, MI355X) moved 4.7 TB/s with the planes apart, 5.2 in
+// pairs and 5.4-5.6 in groups of four and a pair.
 template <typename S>
 __host__ __device__ constexpr int64_t plane_elem(int k, int64_t i, int64_t N) {
-  if constexpr (S::kPaired) {
-    if (k < (S::kPlanes & ~1)) return static_cast<int64_t>(k & ~1) * N + 2 * i + (k & 1);
+  if constexpr (S::kGrouped) {
+    constexpr int q4 = S::kPlanes & ~3;       // planes in groups of four
+    constexpr int q2 = q4 + (S::kPlanes & 2);  // then a pair, if two are left
+    if (k < q4) return static_cast<int64_t>(k & ~3) * N + 4 * i + (k & 3);
+    if (k < q2) return static_cast<int64_t>(q4) * N + 2 * i + (k & 1);
   }
   return static_cast<int64_t>(k) * N + i;
 }

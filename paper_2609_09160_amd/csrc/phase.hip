@@ -167,15 +167,15 @@ __global__ void __launch_bounds__(64 * kUpdRows) phase_kernel(
       const int64_t zu = static_cast<int64_t>(pmod(clampi(qs + i - 1, z0 - 1, z1), nz)) * plane;
 #pragma unroll
       for (int k = 0; k < PERV; ++k) {
-        if constexpr (S::kPaired) {
-          // 16-bit storage: (p*, u_x) and (u_y, u_z) are one 32-bit word each
-          using T = typename S::T;
-          const uint32_t* st32 = reinterpret_cast<const uint32_t*>(st);
-          const uint32_t w0 = buf_load<uint32_t>(plane_rsrc(st32 + zu, 2 * pbytes_t), 2 * voff[k]);
-          const uint32_t w1 = buf_load<uint32_t>(plane_rsrc(st32 + N + zu, 2 * pbytes_t), 2 * voff[k]);
-          ux[b][i][k] = S::decode(static_cast<T>(w0 >> 16), s1);
-          uy[b][i][k] = S::decode(static_cast<T>(w1 & 0xffffu), s2);
-          uz[b][i][k] = S::decode(static_cast<T>(w1 >> 16), s3);
+        if constexpr (S::kGrouped) {
+          // 16-bit storage: p*, u_x, u_y, u_z of a site are one 64-bit word
+          using T4 = typename S::T __attribute__((ext_vector_type(4)));
+          const uint64_t* st64 = reinterpret_cast<const uint64_t*>(st);
+          const T4 h = __builtin_bit_cast(
+              T4, buf_load<uint64_t>(plane_rsrc(st64 + zu, 4 * pbytes_t), 4 * voff[k]));
+          ux[b][i][k] = S::decode(h.y, s1);
+          uy[b][i][k] = S::decode(h.z, s2);
+          uz[b][i][k] = S::decode(h.w, s3);
         } else {
           ux[b][i][k] = S::decode(buf_load<typename S::T>(plane_rsrc(st + N + zu, pbytes_t), voff[k]), s1);
           uy[b][i][k] = S::decode(buf_load<typename S::T>(plane_rsrc(st + 2 * N + zu, pbytes_t), voff[k]), s2);

@@ -281,7 +281,8 @@ struct Forward {
     for (int k = 0; k < ((FNEXT && VAR) ? 6 : 1); ++k) c.M[k] = C(0);
   }
 
-  // two 16-bit words of one site (paired planes 2j, 2j + 1)
+  // the 16-bit values of one site in a group of four planes, or a pair
+  using T4 = T __attribute__((ext_vector_type(4)));
   using T2 = T __attribute__((ext_vector_type(2)));
   // the force field has the compute type; its byte offset scales accordingly
   static constexpr uint32_t kFscale = sizeof(C) / sizeof(T);
@@ -290,25 +291,42 @@ struct Forward {
   static __device__ __forceinline__ void fetch(const StepArgs& a, int64_t pb, uint32_t off,
                                                uint32_t plane_bytes, Raw<OWN> (&r)[NS]) {
     const T* __restrict__ src = static_cast<const T*>(a.src);
-    // 16-bit storage: planes 2j and 2j + 1 as one 32-bit word per site
-    constexpr int kWords = S::kPaired ? S::kPlanes / 2 : 0;
-    if constexpr (S::kPaired) {
+    // 16-bit storage: planes 4j .. 4j + 3 as one 64-bit word per site, then
+    // a pair as one 32-bit word (plane_elem)
+    constexpr int kQ4 = S::kGrouped ? (S::kPlanes & ~3) : 0;
+    constexpr int kQ2 = S::kGrouped ? kQ4 + (S::kPlanes & 2) : 0;
+    if constexpr (S::kGrouped) {
 #pragma unroll
-      for (int j = 0; j < kWords; ++j) {
+      for (int j = 0; j < kQ4 / 4; ++j) {
+        uint64_t w[NS];
+        buf_load_n<uint64_t, NS>(
+            plane_rsrc(reinterpret_cast<const uint64_t*>(src) + (j * a.N + pb), 4 * plane_bytes),
+            4 * off, w);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const T4 h = __builtin_bit_cast(T4, w[s]);
+          r[s].m[4 * j] = h.x;
+          r[s].m[4 * j + 1] = h.y;
+          r[s].m[4 * j + 2] = h.z;
+          r[s].m[4 * j + 3] = h.w;
+        }
+      }
+      if constexpr (kQ2 > kQ4) {
         uint32_t w[NS];
         buf_load_n<uint32_t, NS>(
-            plane_rsrc(reinterpret_cast<const uint32_t*>(src) + (j * a.N + pb), 2 * plane_bytes),
+            plane_rsrc(reinterpret_cast<const uint32_t*>(src) + (kQ4 / 2 * a.N + pb),
+                       2 * plane_bytes),
             2 * off, w);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
           const T2 h = __builtin_bit_cast(T2, w[s]);
-          r[s].m[2 * j] = h.x;
-          r[s].m[2 * j + 1] = h.y;
+          r[s].m[kQ4] = h.x;
+          r[s].m[kQ4 + 1] = h.y;
         }
       }
     }
 #pragma unroll
-    for (int k = 2 * kWords; k < S::kPlanes; ++k) {
+    for (int k = kQ2; k < S::kPlanes; ++k) {
       T v[NS];
       buf_load_n<T, NS>(plane_rsrc(src + (k * a.N + pb), plane_bytes), off, v);
 #pragma unroll
@@ -508,23 +526,36 @@ struct Forward {
         for (int k = 0; k < 10; ++k) q[s][k] = S::encode(out[s][k], a.inv_scale[k]);
       }
     }
-    constexpr int kWords = S::kPaired ? S::kPlanes / 2 : 0;
-    if constexpr (S::kPaired) {
+    constexpr int kQ4 = S::kGrouped ? (S::kPlanes & ~3) : 0;
+    constexpr int kQ2 = S::kGrouped ? kQ4 + (S::kPlanes & 2) : 0;
+    if constexpr (S::kGrouped) {
 #pragma unroll
-      for (int j = 0; j < kWords; ++j) {
+      for (int j = 0; j < kQ4 / 4; ++j) {
+        uint64_t w[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          // built as vectors of halves, so that pairs convert in one instruction
+          const T4 h = {q[s][4 * j], q[s][4 * j + 1], q[s][4 * j + 2], q[s][4 * j + 3]};
+          w[s] = __builtin_bit_cast(uint64_t, h);
+        }
+        buf_store_nt_n<uint64_t, NS>(
+            w, plane_rsrc(reinterpret_cast<uint64_t*>(dst) + (j * a.N + pb), 4 * plane_bytes),
+            4 * off);
+      }
+      if constexpr (kQ2 > kQ4) {
         uint32_t w[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-          const T2 h = {q[s][2 * j], q[s][2 * j + 1]};  // one packed conversion
+          const T2 h = {q[s][kQ4], q[s][kQ4 + 1]};
           w[s] = __builtin_bit_cast(uint32_t, h);
         }
         buf_store_nt_n<uint32_t, NS>(
-            w, plane_rsrc(reinterpret_cast<uint32_t*>(dst) + (j * a.N + pb), 2 * plane_bytes),
+            w, plane_rsrc(reinterpret_cast<uint32_t*>(dst) + (kQ4 / 2 * a.N + pb), 2 * plane_bytes),
             2 * off);
       }
     }
 #pragma unroll
-    for (int k = 2 * kWords; k < S::kPlanes; ++k) {
+    for (int k = kQ2; k < S::kPlanes; ++k) {
       T v[NS];
 #pragma unroll
       for (int s = 0; s < NS; ++s) v[s] = q[s][k];

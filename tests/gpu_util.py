@@ -32,16 +32,24 @@ def gpu_run(shape, tau, m0, steps, lattice=19, storage="f64", bc=(0, 0, 0), forc
 
 def stored_planes(words, nplanes, N):
     """The binary16 words of a 16-bit state as [nplanes, N], plane by plane,
-    from the layout the library documents: planes 2j and 2j + 1 interleaved
-    site by site in words [2jN, (2j + 2)N), plane 2j first (the low half of
-    each 32-bit word); a last odd plane on its own after them."""
+    from the layout the library documents: planes 4j .. 4j + 3 interleaved
+    site by site in words [4jN, (4j + 4)N), plane 4j first (the lowest 16
+    bits of each 64-bit word); two planes left over interleaved the same way
+    after the groups; a last single plane on its own."""
     words = np.asarray(words).reshape(-1)[:nplanes * N]
     out = np.empty((nplanes, N), dtype=words.dtype)
-    for j in range(nplanes // 2):
-        pair = words[2 * j * N:(2 * j + 2) * N].reshape(N, 2)
-        out[2 * j], out[2 * j + 1] = pair[:, 0], pair[:, 1]
-    if nplanes % 2:
-        out[-1] = words[(nplanes - 1) * N:nplanes * N]
+    q4 = nplanes & ~3
+    for j in range(q4 // 4):
+        grp = words[4 * j * N:(4 * j + 4) * N].reshape(N, 4)
+        for c in range(4):
+            out[4 * j + c] = grp[:, c]
+    k = q4
+    if nplanes - q4 >= 2:
+        pair = words[q4 * N:(q4 + 2) * N].reshape(N, 2)
+        out[q4], out[q4 + 1] = pair[:, 0], pair[:, 1]
+        k = q4 + 2
+    if k < nplanes:
+        out[k] = words[k * N:(k + 1) * N]
     return out
 
 
