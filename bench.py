@@ -270,9 +270,21 @@ def copy_ceilings(n=512 ** 3, nplanes=10, reps=10):
     planes = lambda: _lib.check(lib.lbfast_planes_probe(A, B, n, nplanes, S))  # noqa: E731
     out = {"bytes_read": nbytes // 2, "bytes_written": nbytes // 2,
            "library_copy_probe_GBs": best(probe),
-           "library_planes_probe_GBs": best(planes),
-           "torch_copy_GBs": best(lambda: b.copy_(a)),
-           "torch_elementwise_GBs": best(lambda: torch.mul(a, 1.0, out=b))}
+           "library_planes_probe_GBs": best(planes)}
+    # the step's marching order over a state of the same sites in each layout
+    # (GB/s counting read + write of the state: 40 B per site in FP32, 20 B at
+    # 16 bits); 16-bit layouts first, so that the FP32 one leaves b == a
+    side = round(n ** (1 / 3))
+    if side ** 3 == n and side % 128 == 0 and nplanes == 10:
+        zm = {}
+        for name, layout, nb in (("16bit_planes", 1, 20), ("16bit_pairs", 2, 20),
+                                 ("16bit_groups_of_four", 3, 20), ("f32_planes", 0, 40)):
+            run = lambda: _lib.check(lib.lbfast_zmarch_probe(  # noqa: E731
+                A, B, side, side, side, layout, min(256, side), S))
+            zm[name] = round(best(run) * nb / 40, 1)
+        out["zmarch_copy_GBs"] = zm
+    out["torch_copy_GBs"] = best(lambda: b.copy_(a))
+    out["torch_elementwise_GBs"] = best(lambda: torch.mul(a, 1.0, out=b))
     assert torch.equal(a[-4096:], b[-4096:])
     del a, b
     torch.cuda.empty_cache()

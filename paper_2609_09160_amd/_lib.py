@@ -88,6 +88,7 @@ def load():
         "lbfast_stream_probe": ([vp, vp, i64, i32, vp], i32),
         "lbfast_copy_probe": ([vp, vp, i64, vp], i32),
         "lbfast_planes_probe": ([vp, vp, i64, i32, vp], i32),
+        "lbfast_zmarch_probe": ([vp, vp, i32, i32, i32, i32, i32, vp], i32),
         "lbfast_enable_two_phase": ([vp, ctypes.POINTER(LbfastPhaseParams)], i32),
         "lbfast_set_phase": ([vp, vp, i32, i32], i32),
         "lbfast_get_phase": ([vp, vp, i32, i32], i32),

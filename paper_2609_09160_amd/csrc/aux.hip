@@ -274,6 +274,65 @@ __global__ void __launch_bounds__(kThreads) copy_planes_kernel(const float* __re
     __builtin_nontemporal_store(v[k], reinterpret_cast<F2*>(dst + k * n + i));
 }
 
+// The step's marching order without halos or arithmetic, for the layouts of
+// a state: a workgroup of 8 waves owns a 128 x 8 column tile (two sites per
+// lane, one row per wave) and a chunk of z-planes, and reads plane z + 1
+// while it writes plane z (non-temporal stores).  Layout L: 0 = ten FP32
+// planes apart, 1 = ten 16-bit planes apart, 2 = 16-bit planes in pairs (a
+// 32-bit word per site), 3 = 16-bit planes in two groups of four and a pair
+// (the library's 16-bit layout: a 64-bit, a 64-bit and a 32-bit word per
+// site).  zm_bytes(L, g) is the bytes per site of stream g.
+constexpr int kZmRows = 8;
+constexpr int zm_streams(int L) { return L <= 1 ? 10 : (L == 2 ? 5 : 3); }
+constexpr int zm_bytes(int L, int g) { return L == 0 ? 4 : (L == 1 ? 2 : (L == 2 ? 4 : (g < 2 ? 8 : 4))); }
+constexpr int zm_prefix(int L, int g) { return g == 0 ? 0 : zm_prefix(L, g - 1) + zm_bytes(L, g - 1); }
+template <int W> struct ZmVec;
+template <> struct ZmVec<4> { using V = unsigned; };
+template <> struct ZmVec<8> { using V = unsigned __attribute__((ext_vector_type(2))); };
+template <> struct ZmVec<16> { using V = unsigned __attribute__((ext_vector_type(4))); };
+
+template <int L>
+__global__ void __launch_bounds__(64 * kZmRows) zmarch_copy_kernel(const char* __restrict__ src,
+                                                                   char* __restrict__ dst, int nx,
+                                                                   int ny, int nz, int zchunk) {
+  constexpr int G = zm_streams(L);
+  constexpr int WORDS = 2 * zm_prefix(L, G) / 4;  // 32-bit words a lane moves per plane
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tiles_x = nx / 128, tiles_y = ny / kZmRows;
+  int b = static_cast<int>(blockIdx.x);
+  const int tx = b % tiles_x;
+  b /= tiles_x;
+  const int ty = b % tiles_y;
+  const int zc = b / tiles_y;
+  const int64_t N = static_cast<int64_t>(nx) * ny * nz, P = static_cast<int64_t>(nx) * ny;
+  const int64_t row = static_cast<int64_t>(ty * kZmRows + w) * nx + tx * 128 + 2 * lane;
+  const int z0 = zc * zchunk, z1 = min(z0 + zchunk, nz);
+  unsigned cur[WORDS], nxt[WORDS];
+  auto load = [&](int z, unsigned (&r)[WORDS]) __attribute__((always_inline)) {
+    const int64_t site = z * P + row;
+    static_for<G>([&](auto I) {
+      constexpr int g = decltype(I)::value, B = zm_bytes(L, g), O = 2 * zm_prefix(L, g) / 4;
+      using V = typename ZmVec<2 * B>::V;
+      const V v = *reinterpret_cast<const V*>(src + zm_prefix(L, g) * N + site * B);
+      __builtin_memcpy(&r[O], &v, 2 * B);
+    });
+  };
+  load(z0, cur);
+  for (int z = z0; z < z1; ++z) {
+    load(min(z + 1, z1 - 1), nxt);
+    const int64_t site = z * P + row;
+    static_for<G>([&](auto I) {
+      constexpr int g = decltype(I)::value, B = zm_bytes(L, g), O = 2 * zm_prefix(L, g) / 4;
+      using V = typename ZmVec<2 * B>::V;
+      V v;
+      __builtin_memcpy(&v, &cur[O], 2 * B);
+      __builtin_nontemporal_store(v, reinterpret_cast<V*>(dst + zm_prefix(L, g) * N + site * B));
+    });
+#pragma unroll
+    for (int k = 0; k < WORDS; ++k) cur[k] = nxt[k];
+  }
+}
+
 Scales to_scales(const float* p) {
   Scales s;
   for (int k = 0; k < 10; ++k) s.v[k] = p[k];
@@ -370,6 +429,26 @@ hipError_t launch_copy_probe(const void* src, void* dst, int64_t n4, hipStream_t
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(copy_wide_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, s,
                      static_cast<const F4*>(src), static_cast<F4*>(dst), n4);
+  return hipGetLastError();
+}
+
+hipError_t launch_zmarch_probe(const void* src, void* dst, int nx, int ny, int nz, int layout,
+                               int zchunk, hipStream_t s) {
+  if (nx < 128 || nx % 128 || ny < kZmRows || ny % kZmRows || nz < 1 || zchunk < 1 ||
+      layout < 0 || layout > 3)
+    return hipErrorInvalidValue;
+  const int64_t blocks =
+      static_cast<int64_t>(nx / 128) * (ny / kZmRows) * ((nz + zchunk - 1) / zchunk);
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>(blocks)), block(64 * kZmRows);
+  const char* a = static_cast<const char*>(src);
+  char* b = static_cast<char*>(dst);
+  switch (layout) {
+    case 0: hipLaunchKernelGGL(zmarch_copy_kernel<0>, grid, block, 0, s, a, b, nx, ny, nz, zchunk); break;
+    case 1: hipLaunchKernelGGL(zmarch_copy_kernel<1>, grid, block, 0, s, a, b, nx, ny, nz, zchunk); break;
+    case 2: hipLaunchKernelGGL(zmarch_copy_kernel<2>, grid, block, 0, s, a, b, nx, ny, nz, zchunk); break;
+    default: hipLaunchKernelGGL(zmarch_copy_kernel<3>, grid, block, 0, s, a, b, nx, ny, nz, zchunk); break;
+  }
   return hipGetLastError();
 }
 

@@ -409,9 +409,10 @@ struct Storage<kF16SU> : Storage<kF16S> {
 // holds the four values of a site, plane 4j in its lowest 16 bits.  Two
 // planes left over form a pair the same way (one 32-bit word per site); a
 // last odd plane stays on its own.  A wave then reads a few wide streams
-// instead of many narrow ones: z-march copies of ten 16-bit planes (2 sites
-// per lane, 512^3, MI355X) moved 4.7 TB/s with the planes apart, 5.2 in
-// pairs and 5.4-5.6 in groups of four and a pair.
+// instead of many narrow ones.  Measured at 512^3 on MI355X: copies of ten
+// 16-bit planes in the step's marching order moved 4.5-4.7 TB/s with the
+// planes apart, 5.1-5.2 in pairs and 5.1-5.6 in groups of four and a pair;
+// the D3Q19 FP16 step ran at 105-112, 114-116 and 120-124 GLUPS.
 template <typename S>
 __host__ __device__ constexpr int64_t plane_elem(int k, int64_t i, int64_t N) {
   if constexpr (S::kGrouped) {

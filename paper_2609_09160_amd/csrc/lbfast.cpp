@@ -20,6 +20,8 @@ namespace lbf {
 // measurement utilities, aux.hip
 hipError_t launch_copy_probe(const void* src, void* dst, int64_t n4, hipStream_t s);
 hipError_t launch_planes_probe(const void* src, void* dst, int64_t n, int nplanes, hipStream_t s);
+hipError_t launch_zmarch_probe(const void* src, void* dst, int nx, int ny, int nz, int layout,
+                               int zchunk, hipStream_t s);
 }  // namespace lbf
 
 namespace {
@@ -428,6 +430,24 @@ int lbfast_planes_probe(const void* src, void* dst, int64_t n, int nplanes, void
   if (nplanes < 1 || nplanes > 10) return fail(LBF_E_ARG, "nplanes must be in [1, 10]");
   hipError_t e = lbf::launch_planes_probe(src, dst, n, nplanes, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "planes probe");
+  return LBF_OK;
+}
+
+int lbfast_zmarch_probe(const void* src, void* dst, int nx, int ny, int nz, int layout,
+                        int zchunk, void* stream) {
+  g_err.clear();
+  if (!src || !dst) return fail(LBF_E_ARG, "null buffer");
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15)
+    return fail(LBF_E_ARG, "buffers must be 16-byte aligned");
+  if (nx < 128 || nx % 128) return fail(LBF_E_ARG, "nx must be a positive multiple of 128");
+  if (ny < 8 || ny % 8) return fail(LBF_E_ARG, "ny must be a positive multiple of 8");
+  if (nz < 1 || zchunk < 1) return fail(LBF_E_ARG, "nz and zchunk must be >= 1");
+  if (layout < 0 || layout > 3) return fail(LBF_E_ARG, "layout must be in [0, 3]");
+  if (static_cast<int64_t>(nx / 128) * (ny / 8) * ((nz + zchunk - 1) / zchunk) > 0x7fffffff)
+    return fail(LBF_E_ARG, "grid too large");
+  hipError_t e = lbf::launch_zmarch_probe(src, dst, nx, ny, nz, layout, zchunk,
+                                          static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "z-march probe");
   return LBF_OK;
 }
 

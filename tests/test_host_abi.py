@@ -154,6 +154,22 @@ def test_valid_params_without_gpu_report_device_error(lib, lattice):
     assert rc == _lib.LBF_E_DEVICE and msg
 
 
+@pytest.mark.parametrize("args,needle", [((4096, 8192, 100, 8, 4, 0, 1), "nx"),
+                                         ((4096, 8192, 128, 12, 4, 0, 1), "ny"),
+                                         ((4096, 8192, 128, 8, 4, 0, 0), "zchunk"),
+                                         ((4096, 8192, 128, 8, 0, 0, 1), "nz"),
+                                         ((4096, 8192, 128, 8, 4, 4, 1), "layout"),
+                                         ((4100, 8192, 128, 8, 4, 3, 1), "aligned"),
+                                         ((0, 8192, 128, 8, 4, 3, 1), "null")])
+def test_zmarch_probe_validation(lib, args, needle):
+    # rejected on the host before any device call (the pointers are never used)
+    a, b, nx, ny, nz, layout, zchunk = args
+    rc = lib.lbfast_zmarch_probe(ctypes.c_void_p(a or None), ctypes.c_void_p(b), nx, ny, nz,
+                                 layout, zchunk, None)
+    assert rc == _lib.LBF_E_ARG
+    assert needle in lib.lbfast_last_error().decode()
+
+
 @pytest.mark.parametrize("n,nplanes,needle", [(3, 10, "even"), (0, 10, "even"),
                                               (8, 0, "nplanes"), (8, 11, "nplanes")])
 def test_planes_probe_validation(lib, n, nplanes, needle):
