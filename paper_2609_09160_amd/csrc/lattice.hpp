@@ -244,10 +244,6 @@ struct Storage<kF64> {
   static __device__ __forceinline__ void store(T* p, int64_t i, C v, float) {
     __builtin_nontemporal_store(v, p + i);
   }
-  static __device__ __forceinline__ void store_at(__amdgpu_buffer_rsrc_t r, uint32_t off, C v,
-                                                 float) {
-    buf_store_nt<T>(v, r, off);
-  }
 };
 template <>
 struct Storage<kF32> {
@@ -262,10 +258,6 @@ struct Storage<kF32> {
   static __device__ __forceinline__ T encode(C v, float) { return v; }
   static __device__ __forceinline__ void store(T* p, int64_t i, C v, float) {
     __builtin_nontemporal_store(v, p + i);
-  }
-  static __device__ __forceinline__ void store_at(__amdgpu_buffer_rsrc_t r, uint32_t off, C v,
-                                                 float) {
-    buf_store_nt<T>(v, r, off);
   }
 };
 
@@ -331,23 +323,16 @@ struct Storage<kF16S> {
     return __builtin_fmaf(f16_bits_to_f32(q), s, 0.0f);
   }
   static __device__ __forceinline__ T encode(C v, float inv_s) { return f32_to_f16_bits(v * inv_s); }
-  // stochastic rounding to binary16 (10 stored significand bits: 13 of
-  // binary32's are dropped; the truncated value converts exactly in the normal
-  // range, below it the conversion rounds to nearest)
-  static __device__ __forceinline__ T encode_sr(C v, float inv_s, uint32_t r) {
-    return f32_to_f16_bits(round_stochastic<13>(v * inv_s, r));
-  }
-  // the same for a value already in storage units
+  // a value already in storage units, rounded to nearest or stochastically
+  // (10 stored significand bits: 13 of binary32's are dropped; the truncated
+  // value converts exactly in the normal range, below it the conversion
+  // rounds to nearest)
   static __device__ __forceinline__ T encode_unit(C v) { return f32_to_f16_bits(v); }
   static __device__ __forceinline__ T encode_unit_sr(C v, uint32_t r) {
     return f32_to_f16_bits(round_stochastic<13>(v, r));
   }
   static __device__ __forceinline__ void store(T* p, int64_t i, C v, float inv_s) {
     __builtin_nontemporal_store(f32_to_f16_bits(v * inv_s), p + i);
-  }
-  static __device__ __forceinline__ void store_at(__amdgpu_buffer_rsrc_t r, uint32_t off, C v,
-                                                 float inv_s) {
-    buf_store_nt<T>(f32_to_f16_bits(v * inv_s), r, off);
   }
 };
 template <>
@@ -363,20 +348,14 @@ struct Storage<kBF16S> {
   }
   static __device__ __forceinline__ C decode(T q, float s) { return bf16_bits_to_f32(q) * s; }
   static __device__ __forceinline__ T encode(C v, float inv_s) { return f32_to_bf16_bits(v * inv_s); }
-  // stochastic rounding to bfloat16 (the upper half of binary32)
-  static __device__ __forceinline__ T encode_sr(C v, float inv_s, uint32_t r) {
-    return static_cast<T>(__float_as_uint(round_stochastic<16>(v * inv_s, r)) >> 16);
-  }
+  // a value already in storage units, rounded to nearest or stochastically
+  // (the stochastic form keeps the upper half of binary32)
   static __device__ __forceinline__ T encode_unit(C v) { return f32_to_bf16_bits(v); }
   static __device__ __forceinline__ T encode_unit_sr(C v, uint32_t r) {
     return static_cast<T>(__float_as_uint(round_stochastic<16>(v, r)) >> 16);
   }
   static __device__ __forceinline__ void store(T* p, int64_t i, C v, float inv_s) {
     __builtin_nontemporal_store(f32_to_bf16_bits(v * inv_s), p + i);
-  }
-  static __device__ __forceinline__ void store_at(__amdgpu_buffer_rsrc_t r, uint32_t off, C v,
-                                                 float inv_s) {
-    buf_store_nt<T>(f32_to_bf16_bits(v * inv_s), r, off);
   }
 };
 
