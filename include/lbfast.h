@@ -252,6 +252,16 @@ int lbfast_set_launch(lbfast_t h, int tile_rows, int z_chunk);
  * results may differ between settings in the last bits. */
 int lbfast_set_lane_sites(lbfast_t h, int sites);
 
+/* Order in which the workgroups of the marching kernels (step, checkpointed
+ * forward pass, adjoint) are handed to the GPU's 8 XCDs (each with its own
+ * L2), for the calls that follow: 0 = automatic (contiguous
+ * tile ranges per XCD for F64 storage and for F32 with LBF_D3Q27 and
+ * LBF_D3Q27H, the hardware's order otherwise, as measured at 512^3),
+ * 1 = the hardware's order (consecutive workgroups on the XCDs in turn),
+ * 2 = a contiguous range of tiles per XCD.  A launch choice only: every
+ * order computes bitwise the same results.  LBF_E_ARG for other values. */
+int lbfast_set_block_order(lbfast_t h, int order);
+
 /* Two-component variant (section 2): a phase field phi in [0, 1] (1: heavy
  * phase) transported by the conservative Allen-Cahn equation, Eq. (2),
  * advanced by forward-time centred-space differences with the D3Q27-weighted

@@ -84,6 +84,7 @@ def load():
         "lbfast_get_scales": ([vp, ctypes.POINTER(ctypes.c_float)], i32),
         "lbfast_set_launch": ([vp, i32, i32], i32),
         "lbfast_set_lane_sites": ([vp, i32], i32),
+        "lbfast_set_block_order": ([vp, i32], i32),
         "lbfast_last_error": ([], ctypes.c_char_p),
         "lbfast_stream_probe": ([vp, vp, i64, i32, vp], i32),
         "lbfast_copy_probe": ([vp, vp, i64, vp], i32),

@@ -160,6 +160,7 @@ struct lbfast_ctx {
   int64_t N = 0;
   uint64_t steps_done = 0;       // steps since create: seeds the stochastic rounding
   int adj_sites = 0, adj_rows = 0;  // adjoint launch shape (0: automatic)
+  int block_order = 0;              // 0 automatic, 1 hardware order, 2 per-XCD ranges
 };
 
 namespace {
@@ -306,8 +307,9 @@ int step_args(const lbfast_ctx* h, lbf::StepArgs* a) {
   // are faster for FP64 (21% for D3Q19, 6% for D3Q27h) and for FP32 D3Q27
   // (3%), the hardware order for 16-bit storage (2-5%); D3Q19 FP32 and its
   // adjoint are equal within 1% and keep the hardware order.
-  a->xcd_remap = h->p.storage == LBF_F64 ||
-                 (h->p.storage == LBF_F32 && h->p.lattice != LBF_D3Q19);
+  a->xcd_remap = h->block_order == 2 ||
+                 (h->block_order == 0 &&
+                  (h->p.storage == LBF_F64 || (h->p.storage == LBF_F32 && h->p.lattice != LBF_D3Q19)));
   a->stochastic = h->p.rounding == LBF_ROUND_STOCHASTIC ||
                   (h->p.rounding == LBF_ROUND_AUTO && h->p.storage == LBF_BF16S);
   if (h->two_phase) {
@@ -713,6 +715,14 @@ int lbfast_set_launch(lbfast_t h, int tile_rows, int z_chunk) {
   if (z_chunk < 0) return fail(LBF_E_ARG, "z_chunk must be >= 0");
   if (tile_rows) h->tile_rows = tile_rows;
   if (z_chunk) h->z_chunk = z_chunk;
+  return LBF_OK;
+}
+
+int lbfast_set_block_order(lbfast_t h, int order) {
+  g_err.clear();
+  if (int rc = check_handle(h)) return rc;
+  if (order < 0 || order > 2) return fail(LBF_E_ARG, "order must be 0, 1 or 2");
+  h->block_order = order;
   return LBF_OK;
 }
 

@@ -110,6 +110,11 @@ class Solver:
             check(self.lib.lbfast_set_lane_sites(self.h, int(lane_sites)))
         check(self.lib.lbfast_set_launch(self.h, int(tile_rows), int(z_chunk)))
 
+    def set_block_order(self, order=0):
+        """Workgroup order over the XCDs: 0 automatic, 1 hardware order,
+        2 contiguous tile ranges per XCD (same results bit for bit)."""
+        check(self.lib.lbfast_set_block_order(self.h, int(order)))
+
     def set_adjoint_launch(self, sites=0, tile_rows=0):
         """Launch shape of the adjoint step (0 = automatic)."""
         check(self.lib.lbfast_set_adjoint_launch(self.h, int(sites), int(tile_rows)))

@@ -157,3 +157,21 @@ def test_launch_shape_invariance(Q):
         d = np.abs(got - ref).max()
         say(f"launch {launch}: max diff {d:.3e} (scale {scale:.3e})")
         assert d <= 1e-6 * scale
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s"])
+def test_block_order_is_bitwise_neutral(storage):
+    """The two workgroup orders over the XCDs compute bitwise the same state
+    (the order is a scheduling choice; each site's arithmetic is unchanged)."""
+    from paper_2609_09160_amd import Solver
+    shape = (200, 37, 21)
+    m0 = inputs.random_state(shape, seed=11)
+    out = []
+    for order in (1, 2):
+        s = Solver(shape, 0.65, storage=storage, bc=(0, 1, 0))
+        s.set_block_order(order)
+        s.set_moments(m0)
+        s.step(3)
+        out.append(s.moments_host())
+        s.close()
+    assert np.array_equal(out[0], out[1])

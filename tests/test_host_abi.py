@@ -124,6 +124,7 @@ def test_null_handle_calls(lib):
     assert lib.lbfast_step(None, 1) == _lib.LBF_E_ARG
     assert lib.lbfast_sync(None) == _lib.LBF_E_ARG
     assert lib.lbfast_set_launch(None, 8, 0) == _lib.LBF_E_ARG
+    assert lib.lbfast_set_block_order(None, 1) == _lib.LBF_E_ARG
     assert lib.lbfast_destroy(None) == _lib.LBF_OK
 
 
