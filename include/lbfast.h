@@ -317,9 +317,10 @@ int lbfast_get_phase(lbfast_t h, void* phi, int dtype, int on_device);
  * holds ceil(nsteps/k) buffers of lbfast_buffer_bytes(p) bytes (device,
  * caller-owned, 256-byte aligned).  lbfast_adjoint then walks the segments
  * backwards: each is recomputed from its checkpoint into work_dev (k + 2
- * buffers of lbfast_buffer_bytes(p): the k recomputed states and two
- * adjoint buffers; see lbfast_adjoint_work_bytes) and swept with one adjoint
- * step per time step.  With every = 1 every state but the final one is a
+ * buffers of lbfast_buffer_bytes(p): the recomputed states and two adjoint
+ * buffers; see lbfast_adjoint_work_bytes) and swept with one adjoint step
+ * per time step.  A segment's end state is the next checkpoint and is not
+ * recomputed, except in the last segment (the final state).  With every = 1 every state but the final one is a
  * checkpoint: the forward steps write straight into their slots (no copies)
  * and the adjoint reads each step's two states from ckpt_dev, recomputing
  * only the last step; the backward pass then costs one adjoint step per time

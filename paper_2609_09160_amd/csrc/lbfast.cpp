@@ -1046,15 +1046,16 @@ int lbfast_adjoint(lbfast_t h, int64_t nsteps, int64_t every, const void* ckpt_d
   for (int64_t seg = nseg - 1; seg >= 0; --seg) {
     const int64_t len = std::min(every, nsteps - seg * every);
     char* ck = static_cast<char*>(const_cast<void*>(ckpt_dev));
-    // with every == 1 all states but the final one are checkpoints, and only
-    // the last segment recomputes its end state
-    const bool stored = every == 1 && seg + 1 < nseg;
+    // a segment's end state is the next checkpoint, except for the last
+    // segment, whose end (the final state) is recomputed; with every == 1
+    // only that one state is recomputed at all
+    const bool end_stored = seg + 1 < nseg;
     auto state = [&](int64_t j) -> void* {  // state at t = seg*every + j
       if (j == 0) return ck + seg * bytes;
-      return stored ? static_cast<void*>(ck + (seg + 1) * bytes)
-                    : static_cast<void*>(work + (j - 1) * bytes);
+      if (j == len && end_stored) return ck + (seg + 1) * bytes;
+      return work + (j - 1) * bytes;
     };
-    for (int64_t j = 0; j < len && !stored; ++j) {  // recompute the segment
+    for (int64_t j = 0; j < (end_stored ? len - 1 : len); ++j) {  // recompute the segment
       fa.src = state(j);
       fa.dst = state(j + 1);
       if (int rc = launch_forward(h, fa)) return rc;
