@@ -353,7 +353,9 @@ def run_adjoint(n=192, steps=500, reps=2):
     # result is the next checkpoint (the last segment recomputes it too)
     nseg = -(-steps // 50)
     recomputed = steps - (nseg - 1)
-    adj_step_ms = (b50 - f50 * recomputed / steps) / steps  # backward minus the recomputation
+    # the adjoint step alone: with every state kept the backward pass runs one
+    # adjoint step per time step and recomputes a single forward step
+    adj_step_ms = (b1 - f1 / steps) / steps
     adj_gbs = ADJ_BYTES_PER_LUP * sites / (adj_step_ms * 1e-3) / 1e9
     return {"mlups": round(sites * steps / (b50 * 1e-3) / 1e6, 1),
             "workload": f"D3Q19 FP32 {n}^3 periodic, tau=0.8, from rest, per-site force "
