@@ -56,3 +56,41 @@ def test_16bit_step_on_ragged_grids(storage, bound, ubound, shape, bc, Q):
     eu = float(np.abs(got[1:4] - want[1:4]).max() / np.abs(want[1:4]).max())
     say(f"{storage} D3Q{Q} {shape} bc={bc}: groups {eg:.2e}, u {eu:.2e}")
     assert eg <= bound and eu <= ubound
+
+
+@pytest.mark.parametrize("storage,bound", [("f16s", 2e-3), ("bf16s", 1.6e-2)])
+@pytest.mark.parametrize("shape,bc,rho,taus", [((37, 11, 6), (0, 0, 0), (1.0, 1.0), None),
+                                               ((200, 9, 5), (0, 1, 0), (0.5, 1.5), (0.65, 1.1))])
+def test_16bit_two_component_step_on_ragged_grids(storage, bound, shape, bc, rho, taus):
+    """The two-component step with a 16-bit state (the phase update reads u
+    from the grouped words), one step from the stored state against the
+    two-component oracle: moment groups as above, phi (FP32) within 1e-5."""
+    from oracle import two_phase as T
+    from paper_2609_09160_amd import Solver
+    sigma, width, diff, tau = 0.03, 4.0, 0.1, 0.8
+    nx, ny, nz = shape
+    rng = np.random.default_rng(sum(shape))
+    phi0 = T.droplet(shape, 3.0, width, center=(nx / 3, ny / 2, nz / 2))
+    m0 = np.zeros((10, nz, ny, nx))
+    m0[0] = 1e-3 * rng.standard_normal((nz, ny, nx))
+    m0[1:4] = 1e-3 * rng.standard_normal((3, nz, ny, nx))
+    m0[4:] = 1e-4 * rng.standard_normal((6, nz, ny, nx))
+    for a, b, k in ((0, 0, 4), (1, 1, 5), (2, 2, 6), (0, 1, 7), (0, 2, 8), (1, 2, 9)):
+        m0[k] += m0[1 + a] * m0[1 + b]
+    s = Solver(shape, tau, storage=storage, bc=bc)
+    s.enable_two_phase(sigma, width, diff, rho=rho, tau=taus if taus is not None else tau)
+    s.set_moments(m0)
+    s.set_phase(np.ascontiguousarray(phi0))
+    start = s.moments_host()
+    phi_start = s.phase().cpu().numpy().astype(np.float64)
+    s.step(1)
+    got, phi = s.moments_host(), s.phase().cpu().numpy().astype(np.float64)
+    s.close()
+    nu = None if taus is None else tuple((t - 0.5) / 3.0 for t in taus)
+    o = T.TwoPhaseOracle(19, shape, tau, sigma, width, diff, bc=bc, rho=rho, nu=nu)
+    o.set_state(start, phi_start)
+    o.step(1)
+    eg = group_rel_err(got, o.moments())
+    ephi = float(np.abs(phi - o.phi).max() / np.abs(o.phi).max())
+    say(f"{storage} two-component {shape} bc={bc} rho={rho}: groups {eg:.2e}, phi {ephi:.2e}")
+    assert eg <= bound and ephi <= 1e-5
