@@ -611,7 +611,8 @@ def main():
     VARIANTS = ((27, "f32", "auto"), (19, "f16s", "auto"), (19, "f16s", "stochastic"),
                 (19, "bf16s", "auto"), (19, "f16su", "auto"), (27, "f16s", "auto"),
                 (27, "f16su", "auto"), (19, "f64", "auto"),
-                ("27h", "f32", "auto"), ("27h", "f16s", "auto"), ("27h", "f64", "auto"))
+                ("27h", "f32", "auto"), ("27h", "f16s", "auto"), ("27h", "f16su", "auto"),
+                ("27h", "f64", "auto"))
 
     def vkey(lat, st, rd):
         return f"d3q{lat}_{st}" + ("_stochastic" if rd == "stochastic" else "")

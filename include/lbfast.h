@@ -85,8 +85,8 @@ enum { LBF_D3Q19 = 19, LBF_D3Q27 = 27, LBF_D3Q27H = 270 };
  * remainder (both to nearest even): 22 significant bits for u, which carries
  * almost all of the 16-bit storage error of a slowly evolving flow.  A state
  * then holds 13 planes of N binary16 words: the ten moment planes (planes
- * 1..3 the hi words), then the lo words of u_x, u_y, u_z.  LBF_D3Q19 and
- * LBF_D3Q27 only, one component, rounding to nearest only.
+ * 1..3 the hi words), then the lo words of u_x, u_y, u_z.  All three
+ * velocity sets, one component, rounding to nearest only.
  * Layout of a 16-bit state (what lbfast_state_ptr points to): planes 4j ..
  * 4j + 3 share the 8 N bytes at offset 8 j N, interleaved by site: the 64-bit
  * word at offset 8 (j N + i) holds the four values of site i, plane 4j in its
@@ -245,8 +245,8 @@ int lbfast_set_launch(lbfast_t h, int tile_rows, int z_chunk);
  * nx is even and at least 128 and the 128-wide tiles leave no more of the
  * last tile empty than 64-wide ones, else 3 where nx is divisible by 3 and
  * at least 192 and 192-wide tiles leave no more empty (F32, LBF_D3Q19 or
- * LBF_D3Q27), else 1; always 1 for LBF_D3Q27H with F64 or F16S storage,
- * where two sites spill registers.  If the
+ * LBF_D3Q27), else 1; always 1 for LBF_D3Q27H with F64 storage, where two
+ * sites spill registers.  If the
  * current tile height does not fit the 160 KiB of LDS with the new setting,
  * the tallest of 8, 6 and 4 rows that does is taken.  Same formulas per site;
  * results may differ between settings in the last bits. */

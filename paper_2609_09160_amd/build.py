@@ -18,6 +18,7 @@ LIB = os.path.join(HERE, "liblbfast.so")
 ARCH = os.environ.get("LBFAST_ARCH", "gfx950")
 
 SOURCES = ["step_h_f64.hip", "step_h_f32.hip", "step_h_f16s.hip", "step_h_bf16s.hip",
+           "step_h_f16su.hip",
            "step_f64.hip", "step_f32.hip", "step_f16s.hip", "step_bf16s.hip", "step_f16su.hip",
            "adjoint_f64.hip", "adjoint_f32.hip", "phase.hip", "aux.hip", "noalloc.hip", "lbfast.cpp"]
 

@@ -17,6 +17,7 @@ hipError_t launch_step_h_f64(int, bool, bool, const StepArgs&, hipStream_t);
 hipError_t launch_step_h_f32(int, bool, bool, const StepArgs&, hipStream_t);
 hipError_t launch_step_h_f16s(int, bool, bool, const StepArgs&, hipStream_t);
 hipError_t launch_step_h_bf16s(int, bool, bool, const StepArgs&, hipStream_t);
+hipError_t launch_step_h_f16su(int, bool, bool, const StepArgs&, hipStream_t);
 
 hipError_t launch_step(int Q, int storage, int tile_rows, bool walls_y, const StepArgs& a,
                        hipStream_t stream) {
@@ -27,6 +28,7 @@ hipError_t launch_step(int Q, int storage, int tile_rows, bool walls_y, const St
       case kF32: return launch_step_h_f32(tile_rows, walls_y, ff, a, stream);
       case kF16S: return launch_step_h_f16s(tile_rows, walls_y, ff, a, stream);
       case kBF16S: return launch_step_h_bf16s(tile_rows, walls_y, ff, a, stream);
+      case kF16SU: return launch_step_h_f16su(tile_rows, walls_y, ff, a, stream);
       default: return hipErrorInvalidValue;
     }
   }

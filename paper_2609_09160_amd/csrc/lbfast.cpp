@@ -125,12 +125,8 @@ int validate(const lbfast_params* p) {
     return fail(LBF_E_ARG, "rounding must be LBF_ROUND_AUTO, _NEAREST or _STOCHASTIC");
   if (p->rounding == LBF_ROUND_STOCHASTIC && !s16)
     return fail(LBF_E_ARG, "stochastic rounding applies to 16-bit storage only");
-  if (p->storage == LBF_F16SU) {
-    if (p->rounding == LBF_ROUND_STOCHASTIC)
-      return fail(LBF_E_ARG, "LBF_F16SU rounds to nearest (its velocity keeps 22 bits)");
-    if (p->lattice == LBF_D3Q27H)
-      return fail(LBF_E_UNSUPPORTED, "LBF_F16SU storage is built for LBF_D3Q19 and LBF_D3Q27");
-  }
+  if (p->storage == LBF_F16SU && p->rounding == LBF_ROUND_STOCHASTIC)
+    return fail(LBF_E_ARG, "LBF_F16SU rounds to nearest (its velocity keeps 22 bits)");
   return LBF_OK;
 }
 
@@ -182,7 +178,7 @@ constexpr size_t kLdsLimit = 160 * 1024;
 // where nx allows it (even, at least one 128-wide tile), 8-row tiles (FP64:
 // 4 rows with two sites per lane, 6 with one) or the tallest that fits the
 // LDS; z-chunks only when the column tiles alone give too few workgroups.
-// D3Q27h in FP64 and FP16 keeps one site per lane: two spill registers there.
+// D3Q27h in FP64 keeps one site per lane: two spill registers there.
 void default_launch(lbfast_ctx* h) {
   // two sites per lane unless 128-wide tiles would leave more of the last
   // tile empty than 64-wide ones; else three (FP32, second-order sets) where
@@ -200,11 +196,10 @@ void default_launch(lbfast_ctx* h) {
     h->lane_sites = 3;
   else
     h->lane_sites = 1;
-  // D3Q27h spills registers with two sites per lane in FP64, and in FP16
-  // (measured at 512^3: 48.3 GLUPS against 53.1 with one site; BF16, which
-  // does not spill, keeps two: 57.8 against 56.8)
-  if (h->p.lattice == LBF_D3Q27H && (h->p.storage == LBF_F64 || h->p.storage == LBF_F16S))
-    h->lane_sites = 1;
+  // D3Q27h spills registers with two sites per lane in FP64.  The 16-bit forms
+  // keep two since their planes are grouped (measured at 512^3, one / two
+  // sites: FP16 65.9 / 68.0 GLUPS, split FP16 61.0 / 67.1, BF16 70.0 / 70.2)
+  if (h->p.lattice == LBF_D3Q27H && h->p.storage == LBF_F64) h->lane_sites = 1;
   h->tile_rows = 4;
   const bool f64 = h->p.storage == LBF_F64;
   const int first = f64 ? (h->lane_sites == 2 ? 4 : 6) : (h->lane_sites == 3 ? 6 : 8);

@@ -36,8 +36,6 @@ def _cuda():
                                                   ("f16su", 2e-3, 2.5e-4)])
 @pytest.mark.parametrize("shape,bc,Q", CASES)
 def test_16bit_step_on_ragged_grids(storage, bound, ubound, shape, bc, Q):
-    if storage == "f16su" and Q == "27h":
-        pytest.skip("split-velocity storage is built for D3Q19 and D3Q27")
     import oracle
     from paper_2609_09160_amd import Solver
     tau = 0.7

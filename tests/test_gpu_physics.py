@@ -36,8 +36,6 @@ def test_16bit_storage_accuracy(Q, storage, bound, sites):
     2e-3 ~ 6e-2); BF16's default, stochastic rounding, makes each rounding
     unbiased and independent, and the error settles near 1.2e-2; it is held
     to 3e-2."""
-    if storage == "f16su" and Q == "27h":
-        pytest.skip("the split-velocity form is built for the second-order sets")
     n = 64
     m0, want = solenoidal_oracle_1000(Q, n)
     got = gpu_run((n, n, n), 0.6, m0, 1000, lattice=Q, storage=storage, launch=(0, 0, sites))
@@ -87,8 +85,6 @@ def test_storage_forms_512_vs_fp64(Q):
     bars = {("f32", "auto"): 1e-5, ("f16s", "nearest"): 4e-3, ("f16s", "stochastic"): 2.5e-3,
             ("bf16s", "stochastic"): 3e-2, ("f16su", "auto"): 1e-3}
     for (storage, rounding), bar in bars.items():
-        if storage == "f16su" and Q == "27h":
-            continue  # the split-velocity form is built for the second-order sets
         u = u_after(storage, rounding)
         e = float(torch.linalg.vector_norm(u - ref)) / ref_norm
         del u
@@ -112,8 +108,6 @@ def test_sampled_sites_512_16bit(Q, storage, bound):
     twice that."""
     import torch
     from paper_2609_09160_amd import Solver
-    if storage == "f16su" and Q == "27h":
-        pytest.skip("the split-velocity form is built for the second-order sets")
     n, tau = 512, 0.6
     m32 = inputs.solenoidal_field((n, n, n), device="cuda").float()
     s = Solver((n, n, n), tau, lattice=Q, storage=storage)
